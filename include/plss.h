@@ -1,0 +1,204 @@
+/* plss.h -- C ABI of the PLSS GPU library (AMD MI355X, gfx950).
+ *
+ * PLSS (Brust & Saunders, "PLSS: A Projected Linear Systems Solver",
+ * arXiv:2207.07615) solves a consistent system A x = b, A (m x n) sparse,
+ * b in range(A) (Section 1, eq. axb), by x_k = x_{k-1} + p_k (eq. xko) where
+ * p_k is the minimum-norm correction satisfying the sketched constraints
+ * S_kᵀ A (x_{k-1} + p_k) = S_kᵀ b (eqs. itProb-cons, closed form eq. pkLong).
+ *
+ *  - Residual sketch S_k = [r_0 ... r_{k-1}] (eq. S): the short recurrence of
+ *    Theorem 2 / Algorithm 1 (one product with A and one with Aᵀ per
+ *    iteration, four vectors).
+ *  - Identity sketch S_k = [e_{i_1} ... e_{i_k}] (Section 7, eq. pkKacz,
+ *    "PLSS Kaczmarz"), with the stored products A p_j.
+ *  - Mixed sketch: residual and identity columns alternate, one row per
+ *    residual column (a sketch of the general form of Section 2).
+ *
+ * Conventions for every call:
+ *  - Return value: plss_status.  0 = success; > 0 = finished with a warning
+ *    (outputs valid); < 0 = error (outputs unspecified).  On error,
+ *    plss_last_error() returns a description (thread-local).
+ *  - Array arguments may point to host memory or to device memory of the
+ *    handle's GPU (unified addressing; the library copies what it needs).
+ *    They are read (or written, for outputs) only during the call.
+ *  - Handles, matrices and servers are owned by the library until their
+ *    *_destroy call.  One handle per host thread; calls on one handle are
+ *    serialised on the handle's HIP stream and return when their work is
+ *    complete.
+ */
+#ifndef PLSS_H
+#define PLSS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PLSS_OK = 0,             /* stop test met */
+  PLSS_NOT_CONVERGED = 1,  /* iteration limit reached; x is the last iterate */
+  PLSS_BREAKDOWN = 2,      /* phi == 0 or sqrt(theta*phi)/rho <= 1 (b not in range(A)
+                              in exact arithmetic); x is the last iterate */
+  PLSS_PENDING = 3,        /* server: request not finished yet */
+  PLSS_EINVAL = -1,        /* malformed argument (CSR, sizes, tolerances, NaN, permutation) */
+  PLSS_ENOMEM = -2,        /* device allocation failed or over the memory budget */
+  PLSS_EDEVICE = -3,       /* HIP runtime error */
+  PLSS_ECANCELLED = -4     /* server: request cancelled */
+} plss_status;
+
+typedef enum {
+  PLSS_SKETCH_RESIDUAL = 0, /* eq. S, Algorithm 1 */
+  PLSS_SKETCH_IDENTITY = 1, /* Section 7 (PLSS KZ) */
+  PLSS_SKETCH_MIXED = 2     /* r_{k-1}, e_{i}, r, e, ... alternating */
+} plss_sketch;
+
+typedef enum {
+  PLSS_F64 = 0, /* values stored and streamed in float64 */
+  PLSS_F32 = 1  /* values stored in float32 (rounded to nearest); products
+                   accumulate in float32; dots, norms, scalars, x and the
+                   refinement residual stay in float64 */
+} plss_dtype;
+
+/* A sparse matrix in CSR form, as given by the caller.  row_ptr has m+1
+ * non-decreasing entries with row_ptr[0] = 0 and row_ptr[m] = nnz; the
+ * column indices of a row are ascending, distinct and in [0, n); values
+ * are finite float64. */
+typedef struct {
+  int64_t m, n, nnz;
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const double* values;
+} plss_csr;
+
+typedef struct {
+  plss_sketch sketch;
+  double tol;           /* stop when ||r|| <= tol*||b|| (or <= tol if tol_absolute);
+                           the stop rule stated after Algorithm 1 */
+  int64_t maxit;        /* at most maxit updates (Algorithm 1's maxIt > 0) */
+  int32_t tol_absolute;
+  int32_t refine;       /* float32 storage: float64 iterative refinement on b - A x */
+  double inner_tol;     /* refinement: relative tolerance of each inner solve */
+  int64_t max_outer;    /* refinement: bound on inner solves */
+  const double* x0;     /* optional start (length n); NULL means x0 = 0 */
+  const double* wi_diag;/* optional diagonal of BᵀB (length n, > 0): W = diag(1/wi)
+                           (Section 4.1); NULL means W = I.  Residual sketch only. */
+  const int32_t* row_perm; /* identity/mixed: order of identity columns, a permutation
+                              of 0..m-1 reused cyclically; NULL means 0..m-1 */
+  int64_t hist_cap;     /* identity/mixed: history columns kept before the stored
+                           P, AP are cleared (0: min(m, n, 256)) */
+  int32_t chunk;        /* iterations per launch batch between host checks (0: auto) */
+  int32_t timing;       /* record per-kernel device times (see plss_kernel_times) */
+} plss_opts;
+
+typedef struct {
+  int64_t iters;        /* updates applied (summed over inner solves) */
+  int64_t outer_iters;  /* inner solves (1 without refinement) */
+  double relres;        /* last recursive residual estimate / ||b|| */
+  double relres_true;   /* ||b - A x|| / ||b|| computed in float64 at exit */
+  int32_t status;       /* plss_status of this system */
+  double ms;            /* device time of the solve (milliseconds) */
+} plss_info;
+
+typedef struct plss_handle plss_handle;
+typedef struct plss_matrix plss_matrix;
+typedef struct plss_server plss_server;
+
+/* Fill opts with defaults: residual sketch, tol 1e-8 relative, maxit 1000,
+ * refine on, inner_tol 1e-4, max_outer 20, everything else 0/NULL. */
+void plss_opts_default(plss_opts* opts);
+
+/* Create a handle on GPU `device` (its own non-blocking stream). */
+plss_status plss_create(plss_handle** h, int device);
+plss_status plss_destroy(plss_handle* h);
+
+/* Upload A and build its device store once: CSR with int32 pointers and the
+ * CSC copy (rows ascending inside every column) used for the products with
+ * Aᵀ (Algorithm 1's y = Aᵀ r), values in `storage` precision, and the tile
+ * tables of both.  Errors: EINVAL for a malformed CSR or nnz >= 2^31,
+ * ENOMEM. */
+plss_status plss_matrix_create(plss_handle* h, const plss_csr* A, plss_dtype storage,
+                               plss_matrix** out);
+plss_status plss_matrix_destroy(plss_matrix* A);
+/* Sizes and device bytes held by the store. */
+plss_status plss_matrix_info(const plss_matrix* A, int64_t* m, int64_t* n, int64_t* nnz,
+                             int64_t* device_bytes);
+/* Copy the CSC copy out: col_ptr (n+1, int64), row_idx (nnz), values (nnz, float64,
+ * widened from the storage precision).  Any pointer may be NULL. */
+plss_status plss_matrix_csc(const plss_matrix* A, int64_t* col_ptr, int32_t* row_idx,
+                            double* values);
+/* Re-tile both directions for the tile width (entries per thread, 4, 8 or
+ * 16) that runs fastest on this device; returns the widths chosen. */
+plss_status plss_matrix_autotune(plss_handle* h, plss_matrix* A, int32_t* csr_width,
+                                 int32_t* csc_width);
+
+/* y = A x (transpose = 0, x length n, y length m) or y = Aᵀ x (transpose = 1),
+ * float64 in and out, float64 accumulation over the stored values. */
+plss_status plss_spmv(plss_handle* h, const plss_matrix* A, int transpose, const double* x,
+                      double* y);
+
+/* Solve A x = b (b length m, x length n).  res_hist (may be NULL) receives
+ * up to hist_cap entries sqrt(rho_k)/||b||, k = 0..iters (the recursive
+ * residual of Algorithm 1).  Returns the system's status (OK, NOT_CONVERGED,
+ * BREAKDOWN) or an error. */
+plss_status plss_solve(plss_handle* h, const plss_matrix* A, const double* b,
+                       const plss_opts* opts, double* x, double* res_hist, int64_t hist_cap,
+                       plss_info* info);
+
+/* Solve nsys independent systems together: every phase of an iteration is
+ * one launch over all unfinished systems.  Each result equals the result of
+ * solving that system alone with plss_solve (the reductions of a system
+ * depend only on its own tiles).  opts, b, x and info are arrays of nsys.
+ * Returns PLSS_OK if every system converged, else the first non-OK status. */
+plss_status plss_solve_batch(plss_handle* h, int32_t nsys, const plss_matrix* const* A,
+                             const double* const* b, const plss_opts* opts, double* const* x,
+                             plss_info* info);
+
+/* Solve A X = B for nrhs right-hand sides (B m x nrhs and X n x nrhs, both
+ * column-major): nrhs independent residual-sketch recurrences whose
+ * products with A and Aᵀ are one sparse x dense block product each.
+ * info: array of nrhs.  Residual sketch only. */
+plss_status plss_solve_multi(plss_handle* h, const plss_matrix* A, int32_t nrhs, const double* B,
+                             const plss_opts* opts, double* X, plss_info* info);
+
+/* Per-kernel device time accumulated while opts.timing was set, and the
+ * number of launches: index 0 = product with A (r <- r - A p), 1 = product
+ * with Aᵀ (y <- Aᵀ r), 2 = step scalars, 3 = vector update.  Resets the
+ * counters. */
+plss_status plss_kernel_times(plss_handle* h, double* ms4, int64_t* launches4);
+
+/* ---- request loop (continuous batching) ----
+ * A server owns a host thread and its own stream on the handle's device.
+ * Submitted systems wait until their device footprint fits under
+ * hbm_budget_bytes and a slot is free, are uploaded and transposed on a side
+ * stream, then join the running batch at the next launch boundary; all
+ * admitted systems advance together.  Finished solutions are copied back and
+ * their memory freed. */
+plss_status plss_server_create(plss_handle* h, size_t hbm_budget_bytes, int32_t max_slots,
+                               plss_server** out);
+/* Queue a system (A is copied; the caller's arrays are free after return).
+ * *req receives the request id.  EINVAL for malformed input, ENOMEM if the
+ * system alone exceeds the budget. */
+plss_status plss_server_submit(plss_server* s, const plss_csr* A, plss_dtype storage,
+                               const double* b, const plss_opts* opts, uint64_t* req);
+/* PLSS_PENDING while running; otherwise writes x (length n, host memory) and
+ * info and releases the request (a second poll returns EINVAL). */
+plss_status plss_server_poll(plss_server* s, uint64_t req, double* x, plss_info* info);
+/* Block until every submitted request has finished. */
+plss_status plss_server_drain(plss_server* s);
+/* Cancel a queued or running request; its poll then returns ECANCELLED. */
+plss_status plss_server_cancel(plss_server* s, uint64_t req);
+/* Server counters: submitted, finished, admitted-now, peak bytes in use. */
+plss_status plss_server_stats(plss_server* s, int64_t* submitted, int64_t* finished,
+                              int64_t* active, int64_t* peak_bytes);
+plss_status plss_server_destroy(plss_server* s);
+
+const char* plss_status_string(plss_status s);
+const char* plss_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PLSS_H */

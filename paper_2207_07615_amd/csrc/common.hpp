@@ -1,0 +1,139 @@
+// Shared definitions of the PLSS GPU library (gfx950 / CDNA4).
+//
+// Device-side layout:
+//  * A is held twice: CSR (rows of A) and CSC (rows of Aᵀ), int32 pointers
+//    and indices, values in float64 or float32 storage.
+//  * Each direction carries a tile table: tile t covers rows
+//    [tile[t], tile[t+1]) with at most kTileNnz(V) stored entries and at most
+//    that many rows, or exactly one row when that row alone is longer.
+//  * Per system, a Desc (plain pointers) and a State (scalars of the
+//    iteration) live in device memory; a launch of any phase kernel walks a
+//    list of (system, tile) pairs, so one launch serves one system or many.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+namespace plss {
+
+constexpr int kWG = 256;           // threads per workgroup (4 wave64)
+constexpr int kWaves = kWG / 64;
+
+// statuses stored in State::status (mirror plss_status of the C ABI)
+constexpr int ST_OK = 0;
+constexpr int ST_NOT_CONVERGED = 1;
+constexpr int ST_BREAKDOWN = 2;
+
+enum SpmvMode : int {
+  MODE_RESID = 0,   // r <- r - A p ; partial rho = sum r^2              (Alg. 1 r update, rho)
+  MODE_TRANS = 1,   // y <- Aᵀ r   ; partial phi = sum y^2 / wi         (Alg. 1 y, phi)
+  MODE_REFINE = 2,  // out <- b - A x (float64) ; partial sum out^2, sum b^2
+  MODE_PLAIN = 3,   // out <- A x (float64 in/out)
+  MODE_AP = 4,      // ap <- A p ; r <- r - ap ; partial rho          (Section 7 storage of A p)
+};
+
+struct State {
+  // Algorithm 1 scalars (float64 always)
+  double rho, phi, theta, beta, gamma;
+  double nb, thr, scale;       // inner right-hand side norm, stop threshold, history scale
+  // refinement (outer) scalars
+  double nu;                   // norm of the current outer residual (1 when unrefined)
+  double nb_out;               // ||b||
+  double tol_out;              // outer tolerance (relative unless tol_abs)
+  double inner_tol;
+  double relres_true;
+  long long k;                 // updates applied in the current inner solve
+  long long k_total;           // updates applied over all inner solves
+  long long maxit;             // bound on k_total
+  long long outer, max_outer;
+  int status;                  // inner status when done
+  int done;                    // inner solve finished
+  int final_status;
+  int final_done;              // whole solve finished (x final, relres_true set)
+  int fresh;                   // next update is the first of an inner solve
+  int tol_abs;
+  double tol;                  // requested tolerance (inner when unrefined)
+  // one-column sketch steps (identity / mixed)
+  long long kh;                // stored history columns
+  long long col;               // sketch columns examined
+  long long hist_cap;          // history capacity
+  int skip;                    // current column skipped
+  int col_kind;                // 0 residual column, 1 identity column
+  int row;                     // identity row of the current column
+  int prev_row;                // row scattered into the dense scratch (-1 none)
+  double sigma, delta;
+};
+
+struct Desc {
+  // CSR of A
+  const int* a_ptr;
+  const int* a_idx;
+  const void* a_val;
+  const int* a_tile;
+  int a_ntiles;
+  // CSC of A (= CSR of Aᵀ)
+  const int* t_ptr;
+  const int* t_idx;
+  const void* t_val;
+  const int* t_tile;
+  int t_ntiles;
+  int m, n;
+  int u_nblk;                  // blocks of the vector-update kernel
+  // iteration vectors (Vec = double for float64 storage, float for float32)
+  void* r;                     // m
+  void* p;                     // n
+  void* y;                     // n
+  double* x;                   // n, inner solution (== xo when unrefined)
+  double* xo;                  // n, solution
+  const double* b;             // m
+  void* c;                     // m, inner right-hand side (float32 mode) or null
+  double* r64;                 // m, float64 residual b - A x
+  const double* wi;            // n, diagonal of BᵀB or null (W = I)
+  // partial sums, one per tile / block
+  double* part_rho;            // a_ntiles
+  double* part_b;              // a_ntiles
+  double* part_phi;            // t_ntiles
+  double* part_theta;          // u_nblk
+  double* hist;
+  long long hist_len;
+  State* st;
+  // one-column sketch state
+  double* P;                   // n x cap, column-major
+  double* AP;                  // m x cap, column-major
+  double* Th;                  // cap
+  double* cv;                  // cap, c = w / Θ
+  double* part_w;              // cap x wblk, partial (AP)ᵀ r
+  int wblk;                    // blocks of the (AP)ᵀ r kernel
+  double* dense;               // n, scratch holding one row of A as a dense vector
+  const int* perm;             // m, identity-sketch row order
+  int sketch;                  // 0 residual, 1 identity, 2 mixed
+  int is_f32;
+};
+
+inline int tile_nnz(int V) { return kWG * V; }
+
+// thread-local error text of the C ABI
+void set_error(const std::string& s);
+
+}  // namespace plss
+
+#define PLSS_HIP(call)                                                            \
+  do {                                                                            \
+    hipError_t e_ = (call);                                                       \
+    if (e_ != hipSuccess) {                                                       \
+      ::plss::set_error(std::string(#call) + ": " + hipGetErrorString(e_));       \
+      throw ::plss::DeviceError();                                                \
+    }                                                                             \
+  } while (0)
+
+namespace plss {
+struct DeviceError {};
+struct InvalidArg {
+  std::string msg;
+};
+struct OutOfMemory {
+  std::string msg;
+};
+}  // namespace plss

@@ -1,0 +1,747 @@
+// Device kernels of the PLSS hot path for gfx950 (CDNA4, wave64).
+//
+// Per inner iteration of Algorithm 1 (W = diag(1/wi) or I):
+//   k_spmv<RESID>  r <- r - A p, partial rho             (one workgroup per CSR tile)
+//   k_spmv<TRANS>  y <- Aᵀ r,   partial phi             (one workgroup per CSC tile)
+//   k_step         rho, phi, theta; stop test; beta, gamma (one workgroup per system)
+//   k_update       p <- beta p + gamma W y; x <- x + p; partial theta
+// Outer (refinement / start / finish) sequence:
+//   k_axpy_out     x <- x + nu d (float32 storage only)
+//   k_spmv<REFINE> r64 <- b - A x in float64
+//   k_outer        nu = ||r64||; finish or (re)start the inner solve
+//   k_start        r <- c = r64 / nu (or b), partial rho, partial ||c||^2
+//
+// Every reduction is a fixed-order tree over fixed tiles: results do not
+// depend on scheduling or on which other systems share the launch.
+#include "kernels.hpp"
+
+#include <climits>
+
+namespace plss {
+
+// ------------------------------------------------------------------ reductions
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the workgroup in a fixed order; the result is valid in every thread.
+template <class T>
+__device__ __forceinline__ T block_sum(T v, T* s_tmp) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s_tmp[w] = v;
+  __syncthreads();
+  T t = s_tmp[0];
+#pragma unroll
+  for (int q = 1; q < kWaves; ++q) t += s_tmp[q];
+  return t;
+}
+
+// Fixed-order sum of a[0..n) by one workgroup (valid in every thread).
+__device__ double block_sum_array(const double* __restrict__ a, int n, double* s_tmp) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < n; i += kWG) v += a[i];
+  return block_sum(v, s_tmp);
+}
+
+// Exclusive segmented scan across the workgroup of (f, v) pairs, where a
+// set flag starts a new segment after the element:
+//   incl_j = f_j ? v_j : incl_{j-1} + v_j,  result_j = incl_{j-1} (0 for j = 0).
+template <class T>
+__device__ __forceinline__ T seg_scan_excl(int f, T v, T* s_v, int* s_f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  T sv = v;
+  int sf = f;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    T ov = __shfl_up(sv, off, 64);
+    int of = __shfl_up(sf, off, 64);
+    if (lane >= off) {
+      if (!sf) sv = ov + sv;
+      sf |= of;
+    }
+  }
+  if (lane == 63) {
+    s_v[w] = sv;
+    s_f[w] = sf;
+  }
+  __syncthreads();
+  T pv = T(0);
+  for (int q = 0; q < w; ++q) pv = s_f[q] ? s_v[q] : pv + s_v[q];
+  T incl = sf ? sv : pv + sv;
+  T ex = __shfl_up(incl, 1, 64);
+  if (lane == 0) ex = pv;
+  return ex;
+}
+
+// ------------------------------------------------------------------ phase guards
+
+// phase: the inner iteration runs while final_done == 0 and done == 0.
+template <int MODE>
+__device__ __forceinline__ bool spmv_skip(const State* st) {
+  if (MODE == MODE_PLAIN) return false;
+  if (MODE == MODE_REFINE) return st->final_done || !st->done;
+  if (st->final_done || st->done) return true;
+  if (MODE == MODE_RESID) return st->k == 0;
+  if (MODE == MODE_AP) return st->skip != 0;
+  return false;
+}
+
+// ------------------------------------------------------------------ tile SpMV
+
+template <class Val, class Vin, class Acc, int MODE, int V>
+__global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
+                                              const int2* __restrict__ list, int transpose) {
+  constexpr int T = kWG * V;
+  __shared__ Acc s_prod[T];
+  __shared__ Acc s_row[T];
+  __shared__ int s_off[T + 1];
+  __shared__ Acc s_sv[kWaves];
+  __shared__ int s_sf[kWaves];
+  __shared__ double s_red[kWaves];
+
+  const int2 ent = list[blockIdx.x];
+  const Desc* d = D + ent.x;
+  const State* st = d->st;
+  if (spmv_skip<MODE>(st)) return;
+
+  const bool tr = (MODE == MODE_TRANS) || (MODE == MODE_PLAIN && transpose);
+  const int* __restrict__ ptr = tr ? d->t_ptr : d->a_ptr;
+  const int* __restrict__ idx = tr ? d->t_idx : d->a_idx;
+  const Val* __restrict__ val = static_cast<const Val*>(tr ? d->t_val : d->a_val);
+  const int* __restrict__ tile = tr ? d->t_tile : d->a_tile;
+
+  const Vin* __restrict__ xin;
+  if (MODE == MODE_RESID) xin = static_cast<const Vin*>(d->p);
+  else if (MODE == MODE_TRANS) xin = static_cast<const Vin*>(d->r);
+  else if (MODE == MODE_REFINE) xin = reinterpret_cast<const Vin*>(d->xo);
+  else if (MODE == MODE_PLAIN) xin = static_cast<const Vin*>(d->p);
+  else xin = reinterpret_cast<const Vin*>(d->P + (size_t)st->kh * d->n);
+
+  const int t = ent.y;
+  const int r0 = tile[t], r1 = tile[t + 1];
+  const int e0 = ptr[r0];
+  const int nr = r1 - r0, ne = ptr[r1] - e0;
+
+  double part = 0.0, part2 = 0.0;
+
+  // Row epilogue: the fused vector work of each mode.
+  auto epi = [&](int i, Acc s) {
+    if (MODE == MODE_RESID) {
+      using Vec = Vin;
+      Vec* r = static_cast<Vec*>(d->r);
+      Acc rn = Acc(r[i]) - s;
+      r[i] = Vec(rn);
+      part += double(rn) * double(rn);
+    } else if (MODE == MODE_AP) {
+      double* r = static_cast<double*>(d->r);
+      double rn = r[i] - double(s);
+      r[i] = rn;
+      d->AP[(size_t)st->kh * d->m + i] = double(s);
+      part += rn * rn;
+    } else if (MODE == MODE_TRANS) {
+      using Vec = Vin;
+      static_cast<Vec*>(d->y)[i] = Vec(s);
+      double ds = double(Vec(s));
+      part += d->wi ? ds * ds / d->wi[i] : ds * ds;
+    } else if (MODE == MODE_REFINE) {
+      double bi = d->b[i];
+      double ri = bi - double(s);
+      d->r64[i] = ri;
+      part += ri * ri;
+      part2 += bi * bi;
+    } else {
+      d->r64[i] = double(s);
+    }
+  };
+
+  if (ne > T) {
+    // one row longer than a tile: the whole workgroup strides over it
+    Acc acc = Acc(0);
+    for (int e = threadIdx.x; e < ne; e += kWG)
+      acc += Acc(__builtin_nontemporal_load(&val[e0 + e])) *
+             Acc(xin[__builtin_nontemporal_load(&idx[e0 + e])]);
+    acc = block_sum(acc, s_sv);
+    if (threadIdx.x == 0) epi(r0, acc);
+  } else {
+    for (int i = threadIdx.x; i <= nr; i += kWG) s_off[i] = ptr[r0 + i] - e0;
+    // phase 1: stream the tile's entries (coalesced), gather x, stage products
+#pragma unroll
+    for (int u = 0; u < V; ++u) {
+      const int e = u * kWG + threadIdx.x;
+      if (e < ne)
+        s_prod[e] = Acc(__builtin_nontemporal_load(&val[e0 + e])) *
+                    Acc(xin[__builtin_nontemporal_load(&idx[e0 + e])]);
+    }
+    __syncthreads();
+    // phase 2: each thread sums V consecutive products, split at row ends
+    const int c0 = threadIdx.x * V;
+    Acc acc = Acc(0), first_val = Acc(0);
+    int first_row = -1, has_end = 0;
+    if (c0 < ne) {
+      const int c1 = min(c0 + V, ne);
+      int lo = 0, hi = nr;  // s_off[lo] <= c0 < s_off[hi]
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (s_off[mid] <= c0) lo = mid;
+        else hi = mid;
+      }
+      int rr = lo;
+      int rend = s_off[rr + 1];
+      for (int e = c0; e < c1; ++e) {
+        acc += s_prod[e];
+        if (e + 1 == rend) {
+          if (!has_end) {
+            first_row = rr;
+            first_val = acc;
+            has_end = 1;
+          } else {
+            s_row[rr] = acc;
+          }
+          acc = Acc(0);
+          ++rr;
+          while (rr < nr && s_off[rr + 1] == s_off[rr]) ++rr;
+          rend = (rr < nr) ? s_off[rr + 1] : INT_MAX;
+        }
+      }
+    }
+    const Acc carry = seg_scan_excl<Acc>(has_end, acc, s_sv, s_sf);
+    if (first_row >= 0) s_row[first_row] = first_val + carry;
+    for (int i = threadIdx.x; i < nr; i += kWG)
+      if (s_off[i] == s_off[i + 1]) s_row[i] = Acc(0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nr; i += kWG) epi(r0 + i, s_row[i]);
+  }
+
+  if (MODE == MODE_PLAIN) return;
+  part = block_sum(part, s_red);
+  if (MODE == MODE_REFINE) part2 = block_sum(part2, s_red);
+  if (threadIdx.x == 0) {
+    if (MODE == MODE_TRANS) d->part_phi[t] = part;
+    else d->part_rho[t] = part;
+    if (MODE == MODE_REFINE) d->part_b[t] = part2;
+  }
+}
+
+// ------------------------------------------------------------------ outer sequence
+
+// x <- x + nu d ; d <- 0   (float32 storage, after an inner solve)
+__global__ __launch_bounds__(kWG) void k_axpy_out(const Desc* __restrict__ D,
+                                                  const int2* __restrict__ list) {
+  const int2 ent = list[blockIdx.x];
+  const Desc* d = D + ent.x;
+  const State* st = d->st;
+  if (st->final_done || !st->done || !d->is_f32) return;
+  const double nu = st->nu;
+  const int base = ent.y * (kWG * 4);
+  for (int u = 0; u < 4; ++u) {
+    const int j = base + u * kWG + threadIdx.x;
+    if (j < d->n) {
+      d->xo[j] += nu * d->x[j];
+      d->x[j] = 0.0;
+    }
+  }
+}
+
+// nu = ||b - A x||; finish, or start a new inner solve.
+__global__ __launch_bounds__(kWG) void k_outer(const Desc* __restrict__ D, const int* __restrict__ sys) {
+  __shared__ double s_red[kWaves];
+  const Desc* d = D + sys[blockIdx.x];
+  State* st = d->st;
+  if (st->final_done || !st->done) return;
+  const double rr = block_sum_array(d->part_rho, d->a_ntiles, s_red);
+  const double bb = block_sum_array(d->part_b, d->a_ntiles, s_red);
+  if (threadIdx.x != 0) return;
+  const double nu = sqrt(rr);
+  if (st->outer == 0) st->nb_out = sqrt(bb);
+  const double nbo = st->nb_out;
+  const double rel = (st->tol_abs || nbo == 0.0) ? nu : nu / nbo;
+  st->relres_true = rel;
+  const bool converged = rel <= st->tol_out;
+  if (st->outer == 0) {
+    // before any inner solve: x0 may already satisfy the stop test
+    if (converged) {
+      st->final_status = ST_OK;
+      st->final_done = 1;
+      return;
+    }
+  } else if (!d->is_f32) {
+    // float64 storage: one inner solve; its status stands (Algorithm 1 stops
+    // on the recursively updated residual), the true residual is reported
+    st->final_status = st->status;
+    st->final_done = 1;
+    return;
+  } else if (converged) {
+    st->final_status = ST_OK;
+    st->final_done = 1;
+    return;
+  } else if (st->outer >= st->max_outer || st->k_total >= st->maxit ||
+             st->status == ST_BREAKDOWN || !(nu < st->nu)) {
+    st->final_status = (st->status == ST_BREAKDOWN) ? ST_BREAKDOWN : ST_NOT_CONVERGED;
+    st->final_done = 1;
+    return;
+  }
+  // (re)start the inner solve
+  st->nu = d->is_f32 ? nu : 1.0;
+  st->k = 0;
+  st->done = 0;
+  st->status = ST_OK;
+  st->fresh = 1;
+  st->outer += 1;
+}
+
+// r <- c (inner right-hand side), partial rho and ||c||^2, on the CSR tiles.
+template <class Vec>
+__global__ __launch_bounds__(kWG) void k_start(const Desc* __restrict__ D, const int2* __restrict__ list) {
+  __shared__ double s_red[kWaves];
+  const int2 ent = list[blockIdx.x];
+  const Desc* d = D + ent.x;
+  const State* st = d->st;
+  if (st->final_done || st->done || st->k != 0) return;
+  const int r0 = d->a_tile[ent.y], r1 = d->a_tile[ent.y + 1];
+  const double inv = d->is_f32 ? 1.0 / st->nu : 1.0;
+  Vec* r = static_cast<Vec*>(d->r);
+  Vec* c = static_cast<Vec*>(d->c);
+  double part = 0.0;
+  for (int i = r0 + threadIdx.x; i < r1; i += kWG) {
+    const Vec ci = Vec(d->r64[i] * inv);
+    r[i] = ci;
+    if (c) c[i] = ci;
+    part += double(ci) * double(ci);
+  }
+  part = block_sum(part, s_red);
+  if (threadIdx.x == 0) {
+    d->part_rho[ent.y] = part;
+    d->part_b[ent.y] = part;
+  }
+}
+
+// ------------------------------------------------------------------ inner step scalars
+
+// Algorithm 1: rho, stop test, phi, theta, beta, gamma (one workgroup per system).
+__global__ __launch_bounds__(kWG) void k_step(const Desc* __restrict__ D, const int* __restrict__ sys) {
+  __shared__ double s_red[kWaves];
+  const Desc* d = D + sys[blockIdx.x];
+  State* st = d->st;
+  if (st->final_done || st->done) return;
+  const double rho = block_sum_array(d->part_rho, d->a_ntiles, s_red);
+  const double phi = block_sum_array(d->part_phi, d->t_ntiles, s_red);
+  const long long k = st->k;
+  double theta = 0.0;
+  if (k > 0) theta = block_sum_array(d->part_theta, d->u_nblk, s_red);
+  double nbi = 0.0;
+  if (k == 0) nbi = block_sum_array(d->part_b, d->a_ntiles, s_red);
+  if (threadIdx.x != 0) return;
+
+  if (k == 0) {
+    // inner right-hand side norm and thresholds
+    const double nb = sqrt(nbi);
+    st->nb = nb;
+    if (d->is_f32) {
+      // inner target relative to ||c||; no tighter than the outer target needs
+      double eta = st->inner_tol;
+      const double need = 0.5 * st->tol_out * (st->tol_abs ? 1.0 : st->nb_out) / st->nu;
+      if (need > eta) eta = need;
+      st->thr = eta * nb;
+    } else {
+      st->thr = st->tol_abs ? st->tol : st->tol * st->nb_out;
+    }
+    st->scale = (st->tol_abs || st->nb_out == 0.0) ? st->nu : st->nu / st->nb_out;
+  }
+  const long long kt = st->k_total;
+  if (kt < d->hist_len) d->hist[kt] = sqrt(rho) * st->scale;
+  st->rho = rho;
+  if (sqrt(rho) <= st->thr) {
+    st->status = ST_OK;
+    st->done = 1;
+    return;
+  }
+  if (kt >= st->maxit) {
+    st->status = ST_NOT_CONVERGED;
+    st->done = 1;
+    return;
+  }
+  st->phi = phi;
+  double beta, gamma;
+  if (k == 0) {
+    if (!(phi > 0.0)) {
+      st->status = ST_BREAKDOWN;
+      st->done = 1;
+      return;
+    }
+    beta = 0.0;
+    gamma = rho / phi;
+  } else {
+    st->theta = theta;
+    const double s = sqrt(theta * phi) / rho;
+    if (!(s > 1.0)) {
+      st->status = ST_BREAKDOWN;
+      st->done = 1;
+      return;
+    }
+    beta = 1.0 / ((s - 1.0) * (s + 1.0));
+    gamma = (theta / rho) * beta;
+  }
+  st->beta = beta;
+  st->gamma = gamma;
+  st->fresh = (k == 0);
+  st->k = k + 1;
+  st->k_total = kt + 1;
+}
+
+// p <- beta p + gamma W y ; x <- x + p ; partial theta = p^T (WI p)
+template <class Vec>
+__global__ __launch_bounds__(kWG) void k_update(const Desc* __restrict__ D, const int2* __restrict__ list) {
+  __shared__ double s_red[kWaves];
+  const int2 ent = list[blockIdx.x];
+  const Desc* d = D + ent.x;
+  const State* st = d->st;
+  if (st->final_done || st->done) return;
+  const double beta = st->beta, gamma = st->gamma;
+  const bool fresh = st->fresh != 0;
+  Vec* __restrict__ p = static_cast<Vec*>(d->p);
+  const Vec* __restrict__ y = static_cast<const Vec*>(d->y);
+  double* __restrict__ x = d->x;
+  const double* __restrict__ wi = d->wi;
+  const int n = d->n;
+  const int base = ent.y * (kWG * 4);
+  double part = 0.0;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = base + u * kWG + threadIdx.x;
+    if (j < n) {
+      const double w = wi ? wi[j] : 1.0;
+      const double wy = wi ? double(y[j]) / w : double(y[j]);
+      const double pn = fresh ? gamma * wy : beta * double(p[j]) + gamma * wy;
+      const Vec pv = Vec(pn);
+      p[j] = pv;
+      x[j] += double(pv);
+      part += double(pv) * double(pv) * w;
+    }
+  }
+  part = block_sum(part, s_red);
+  if (threadIdx.x == 0) d->part_theta[ent.y] = part;
+}
+
+// ------------------------------------------------------------------ CSC builder
+
+__global__ void k_csc_count(const int* __restrict__ idx, long long nnz, int* __restrict__ cnt) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nnz;
+       e += (long long)gridDim.x * blockDim.x)
+    atomicAdd(&cnt[idx[e]], 1);
+}
+
+// exclusive scan, stage 1: per-block sums of 1024-element chunks
+__global__ __launch_bounds__(kWG) void k_scan_blocks(const int* __restrict__ in, int n,
+                                                     long long* __restrict__ bsum) {
+  __shared__ long long s_red[kWaves];
+  long long v = 0;
+  const int base = blockIdx.x * 1024;
+  for (int u = 0; u < 4; ++u) {
+    const int i = base + u * kWG + threadIdx.x;
+    if (i < n) v += in[i];
+  }
+  v = block_sum(v, s_red);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = v;
+}
+
+// stage 2: serial exclusive scan of the block sums (single thread; <= a few thousand)
+__global__ void k_scan_top(long long* bsum, int nb) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  long long s = 0;
+  for (int i = 0; i < nb; ++i) {
+    const long long v = bsum[i];
+    bsum[i] = s;
+    s += v;
+  }
+  bsum[nb] = s;
+}
+
+// stage 3: exclusive scan inside each chunk: out[i] = bsum[blk] + sum in[chunk start..i)
+__global__ __launch_bounds__(kWG) void k_scan_apply(const int* __restrict__ in, int n,
+                                                    const long long* __restrict__ bsum,
+                                                    int* __restrict__ out) {
+  __shared__ long long s_t[kWG];
+  const int base = blockIdx.x * 1024 + threadIdx.x * 4;
+  long long loc[4];
+  long long s = 0;
+  for (int u = 0; u < 4; ++u) {
+    loc[u] = s;
+    const int i = base + u;
+    s += (i < n) ? in[i] : 0;
+  }
+  s_t[threadIdx.x] = s;
+  __syncthreads();
+  // Hillis-Steele inclusive scan over the 256 thread totals
+  for (int off = 1; off < kWG; off <<= 1) {
+    long long v = (threadIdx.x >= off) ? s_t[threadIdx.x - off] : 0;
+    __syncthreads();
+    s_t[threadIdx.x] += v;
+    __syncthreads();
+  }
+  const long long pre = bsum[blockIdx.x] + s_t[threadIdx.x] - s;
+  for (int u = 0; u < 4; ++u) {
+    const int i = base + u;
+    if (i < n) out[i] = (int)(pre + loc[u]);
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = (int)bsum[gridDim.x];
+}
+
+// scatter (row, position) of every entry into its column's segment; the order
+// inside a segment is arbitrary and fixed afterwards by k_csc_sort
+__global__ __launch_bounds__(kWG) void k_csc_scatter(const int* __restrict__ ptr,
+                                                     const int* __restrict__ idx, int m,
+                                                     int* __restrict__ cursor,
+                                                     int* __restrict__ row_out,
+                                                     int* __restrict__ pos_out) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * kWG + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * kWG) >> 6;
+  for (int i = wave; i < m; i += nwaves) {
+    for (int e = ptr[i] + lane; e < ptr[i + 1]; e += 64) {
+      const int slot = atomicAdd(&cursor[idx[e]], 1);
+      row_out[slot] = i;
+      pos_out[slot] = e;
+    }
+  }
+}
+
+// sort each column segment by row (rows are distinct inside a column, so the
+// rank of an entry is the number of smaller rows): one wave per column
+__global__ __launch_bounds__(kWG) void k_csc_sort(const int* __restrict__ cptr, int n,
+                                                  const int* __restrict__ row_in,
+                                                  const int* __restrict__ pos_in,
+                                                  int* __restrict__ row_out,
+                                                  int* __restrict__ pos_out) {
+  constexpr int kCap = 512;
+  __shared__ int s_key[kWaves][kCap];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wave = (blockIdx.x * kWG + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * kWG) >> 6;
+  for (int j = wave; j < n; j += nwaves) {
+    const int b = cptr[j], len = cptr[j + 1] - b;
+    if (len <= kCap) {
+      for (int q = lane; q < len; q += 64) s_key[w][q] = row_in[b + q];
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      for (int q = lane; q < len; q += 64) {
+        const int key = s_key[w][q];
+        int rank = 0;
+        for (int o = 0; o < len; ++o) rank += s_key[w][o] < key;
+        row_out[b + rank] = key;
+        pos_out[b + rank] = pos_in[b + q];
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    } else {
+      for (int q = lane; q < len; q += 64) {
+        const int key = row_in[b + q];
+        int rank = 0;
+        for (int o = 0; o < len; ++o) rank += row_in[b + o] < key;
+        row_out[b + rank] = key;
+        pos_out[b + rank] = pos_in[b + q];
+      }
+    }
+  }
+}
+
+template <class Val>
+__global__ void k_gather_vals(const int* __restrict__ pos, long long nnz, const double* __restrict__ src,
+                              Val* __restrict__ dst) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nnz;
+       e += (long long)gridDim.x * blockDim.x)
+    dst[e] = Val(src[pos[e]]);
+}
+
+template <class Val>
+__global__ void k_convert_vals(const double* __restrict__ src, long long nnz, Val* __restrict__ dst) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nnz;
+       e += (long long)gridDim.x * blockDim.x)
+    dst[e] = Val(src[e]);
+}
+
+__global__ void k_ptr64_to_32(const long long* __restrict__ src, int n1, int* __restrict__ dst) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n1; i += gridDim.x * blockDim.x)
+    dst[i] = (int)src[i];
+}
+
+// ------------------------------------------------------------------ host wrappers
+
+static int grid_for(long long work, int per_block = kWG * 4) {
+  long long g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (int)g;
+}
+
+template <class Val, class Vin, class Acc, int MODE>
+static void spmv_v(int V, const Desc* d, const int2* list, int n, int transpose, hipStream_t s) {
+  switch (V) {
+    case 4: k_spmv<Val, Vin, Acc, MODE, 4><<<n, kWG, 0, s>>>(d, list, transpose); break;
+    case 8: k_spmv<Val, Vin, Acc, MODE, 8><<<n, kWG, 0, s>>>(d, list, transpose); break;
+    case 16: k_spmv<Val, Vin, Acc, MODE, 16><<<n, kWG, 0, s>>>(d, list, transpose); break;
+    default: throw InvalidArg{"unsupported tile width"};
+  }
+}
+
+void launch_spmv(int mode, bool f32, int V, const Desc* d, const int2* list, int n, int transpose,
+                 hipStream_t s) {
+  if (n <= 0) return;
+  if (!f32) {
+    switch (mode) {
+      case MODE_RESID: spmv_v<double, double, double, MODE_RESID>(V, d, list, n, 0, s); break;
+      case MODE_TRANS: spmv_v<double, double, double, MODE_TRANS>(V, d, list, n, 1, s); break;
+      case MODE_REFINE: spmv_v<double, double, double, MODE_REFINE>(V, d, list, n, 0, s); break;
+      case MODE_PLAIN: spmv_v<double, double, double, MODE_PLAIN>(V, d, list, n, transpose, s); break;
+      case MODE_AP: spmv_v<double, double, double, MODE_AP>(V, d, list, n, 0, s); break;
+    }
+  } else {
+    switch (mode) {
+      case MODE_RESID: spmv_v<float, float, float, MODE_RESID>(V, d, list, n, 0, s); break;
+      case MODE_TRANS: spmv_v<float, float, float, MODE_TRANS>(V, d, list, n, 1, s); break;
+      case MODE_REFINE: spmv_v<float, double, double, MODE_REFINE>(V, d, list, n, 0, s); break;
+      case MODE_PLAIN: spmv_v<float, double, double, MODE_PLAIN>(V, d, list, n, transpose, s); break;
+      default: throw InvalidArg{"mode not available for float32 storage"};
+    }
+  }
+  PLSS_HIP(hipGetLastError());
+}
+
+void launch_axpy_out(const Desc* d, const int2* ulist, int n, hipStream_t s) {
+  if (n <= 0) return;
+  k_axpy_out<<<n, kWG, 0, s>>>(d, ulist);
+}
+void launch_outer(const Desc* d, const int* sys, int n, hipStream_t s) {
+  if (n <= 0) return;
+  k_outer<<<n, kWG, 0, s>>>(d, sys);
+}
+void launch_start(bool f32, const Desc* d, const int2* alist, int n, hipStream_t s) {
+  if (n <= 0) return;
+  if (f32) k_start<float><<<n, kWG, 0, s>>>(d, alist);
+  else k_start<double><<<n, kWG, 0, s>>>(d, alist);
+}
+void launch_step(const Desc* d, const int* sys, int n, hipStream_t s) {
+  if (n <= 0) return;
+  k_step<<<n, kWG, 0, s>>>(d, sys);
+}
+void launch_update(bool f32, const Desc* d, const int2* ulist, int n, hipStream_t s) {
+  if (n <= 0) return;
+  if (f32) k_update<float><<<n, kWG, 0, s>>>(d, ulist);
+  else k_update<double><<<n, kWG, 0, s>>>(d, ulist);
+}
+
+void build_csc(const int* ptr, const int* idx, const double* vals64, int m, int n, long long nnz,
+               bool f32, int* cptr, int* ridx, void* cvals, void* work, hipStream_t s) {
+  // work layout: cnt[n] | cursor[n+1] | bsum[nb+1] (int64) | row_tmp[nnz] | pos_tmp[nnz] | pos[nnz]
+  char* w = static_cast<char*>(work);
+  int* cnt = reinterpret_cast<int*>(w);
+  w += sizeof(int) * ((size_t)n + 64);
+  int* cursor = reinterpret_cast<int*>(w);
+  w += sizeof(int) * ((size_t)n + 64);
+  const int nb = (n + 1023) / 1024;
+  long long* bsum = reinterpret_cast<long long*>(w);
+  w += sizeof(long long) * ((size_t)nb + 64);
+  int* row_tmp = reinterpret_cast<int*>(w);
+  w += sizeof(int) * ((size_t)nnz + 64);
+  int* pos_tmp = reinterpret_cast<int*>(w);
+  w += sizeof(int) * ((size_t)nnz + 64);
+  int* pos = reinterpret_cast<int*>(w);
+
+  PLSS_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * (size_t)n, s));
+  if (nnz > 0) k_csc_count<<<grid_for(nnz), kWG, 0, s>>>(idx, nnz, cnt);
+  k_scan_blocks<<<nb, kWG, 0, s>>>(cnt, n, bsum);
+  k_scan_top<<<1, 64, 0, s>>>(bsum, nb);
+  k_scan_apply<<<nb, kWG, 0, s>>>(cnt, n, bsum, cptr);
+  PLSS_HIP(hipMemcpyAsync(cursor, cptr, sizeof(int) * (size_t)n, hipMemcpyDeviceToDevice, s));
+  if (nnz > 0) {
+    k_csc_scatter<<<grid_for((long long)m * 64, kWG), kWG, 0, s>>>(ptr, idx, m, cursor, row_tmp, pos_tmp);
+    k_csc_sort<<<grid_for((long long)n * 64, kWG), kWG, 0, s>>>(cptr, n, row_tmp, pos_tmp, ridx, pos);
+    if (f32) k_gather_vals<float><<<grid_for(nnz), kWG, 0, s>>>(pos, nnz, vals64, static_cast<float*>(cvals));
+    else k_gather_vals<double><<<grid_for(nnz), kWG, 0, s>>>(pos, nnz, vals64, static_cast<double*>(cvals));
+  }
+  PLSS_HIP(hipGetLastError());
+}
+
+size_t csc_work_bytes(int n, long long nnz) {
+  const int nb = (n + 1023) / 1024;
+  return sizeof(int) * ((size_t)n + 64) * 2 + sizeof(long long) * ((size_t)nb + 64) +
+         sizeof(int) * ((size_t)nnz + 64) * 3;
+}
+
+void convert_vals(const double* src, long long nnz, bool f32, void* dst, hipStream_t s) {
+  if (nnz <= 0) return;
+  if (f32) k_convert_vals<float><<<grid_for(nnz), kWG, 0, s>>>(src, nnz, static_cast<float*>(dst));
+  else k_convert_vals<double><<<grid_for(nnz), kWG, 0, s>>>(src, nnz, static_cast<double*>(dst));
+  PLSS_HIP(hipGetLastError());
+}
+
+void ptr64_to_32(const long long* src, int n1, int* dst, hipStream_t s) {
+  k_ptr64_to_32<<<grid_for(n1, kWG), kWG, 0, s>>>(src, n1, dst);
+  PLSS_HIP(hipGetLastError());
+}
+
+}  // namespace plss
+
+namespace plss {
+
+// CSR checks on the device: column indices in range, strictly ascending in a
+// row, values finite.  flags bit 0: index out of range, bit 1: not ascending
+// or duplicate, bit 2: non-finite value.
+__global__ __launch_bounds__(kWG) void k_validate(const long long* __restrict__ ptr,
+                                                  const int* __restrict__ idx,
+                                                  const double* __restrict__ val, int m, int n,
+                                                  int* __restrict__ flags) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * kWG + threadIdx.x) >> 6;
+  const int nwaves = (gridDim.x * kWG) >> 6;
+  int f = 0;
+  for (int i = wave; i < m; i += nwaves) {
+    const long long b = ptr[i], e = ptr[i + 1];
+    for (long long q = b + lane; q < e; q += 64) {
+      const int c = idx[q];
+      if (c < 0 || c >= n) f |= 1;
+      if (q + 1 < e && idx[q + 1] <= c) f |= 2;
+      if (!isfinite(val[q])) f |= 4;
+    }
+  }
+  if (f) atomicOr(flags, f);
+}
+
+int validate_csr_device(const long long* ptr, const int* idx, const double* val, int m, int n,
+                        int* dflag, hipStream_t s) {
+  PLSS_HIP(hipMemsetAsync(dflag, 0, sizeof(int), s));
+  k_validate<<<grid_for((long long)m * 64, kWG), kWG, 0, s>>>(ptr, idx, val, m, n, dflag);
+  PLSS_HIP(hipGetLastError());
+  int hf = 0;
+  PLSS_HIP(hipMemcpyAsync(&hf, dflag, sizeof(int), hipMemcpyDeviceToHost, s));
+  PLSS_HIP(hipStreamSynchronize(s));
+  return hf;
+}
+
+}  // namespace plss
+
+namespace plss {
+
+// flag = 1 if any entry is not finite (or, with positive != 0, not > 0)
+__global__ void k_check(const double* __restrict__ a, long long n, int positive, int* __restrict__ flag) {
+  int f = 0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = a[i];
+    if (!isfinite(v) || (positive && !(v > 0.0))) f = 1;
+  }
+  if (f) atomicOr(flag, 1);
+}
+
+void launch_check(const double* a, long long n, int positive, int* flag, hipStream_t s) {
+  if (n <= 0) return;
+  k_check<<<grid_for(n), kWG, 0, s>>>(a, n, positive, flag);
+  PLSS_HIP(hipGetLastError());
+}
+
+}  // namespace plss

@@ -1,0 +1,40 @@
+// Host-side launchers of the device kernels (kernels.hip, sketch.hip, multi.hip).
+#pragma once
+
+#include "common.hpp"
+
+namespace plss {
+
+// tile SpMV family; `list` holds (system, tile) pairs, n of them
+void launch_spmv(int mode, bool f32, int V, const Desc* d, const int2* list, int n, int transpose,
+                 hipStream_t s);
+void launch_axpy_out(const Desc* d, const int2* ulist, int n, hipStream_t s);
+void launch_outer(const Desc* d, const int* sys, int n, hipStream_t s);
+void launch_start(bool f32, const Desc* d, const int2* alist, int n, hipStream_t s);
+void launch_step(const Desc* d, const int* sys, int n, hipStream_t s);
+void launch_update(bool f32, const Desc* d, const int2* ulist, int n, hipStream_t s);
+
+// CSC (transpose) builder: device CSR (int32) -> device CSC, rows ascending in
+// every column; values gathered from the float64 input and stored as f32/f64
+void build_csc(const int* ptr, const int* idx, const double* vals64, int m, int n, long long nnz,
+               bool f32, int* cptr, int* ridx, void* cvals, void* work, hipStream_t s);
+size_t csc_work_bytes(int n, long long nnz);
+void convert_vals(const double* src, long long nnz, bool f32, void* dst, hipStream_t s);
+void ptr64_to_32(const long long* src, int n1, int* dst, hipStream_t s);
+
+// one-column sketch steps (identity / mixed)
+void launch_sketch_step(const Desc* d, int ndesc_unused, int V, const int2* alist, int na,
+                        const int2* tlist, int nt, const int2* ulist, int nu, const int2* wlist,
+                        int nw, const int* sys, int ns, bool residual_column, hipStream_t s);
+
+}  // namespace plss
+
+namespace plss {
+// returns the flag bits of k_validate (0 = well formed)
+int validate_csr_device(const long long* ptr, const int* idx, const double* val, int m, int n,
+                        int* dflag, hipStream_t s);
+}  // namespace plss
+
+namespace plss {
+void launch_check(const double* a, long long n, int positive, int* flag, hipStream_t s);
+}  // namespace plss

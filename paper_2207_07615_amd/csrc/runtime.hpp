@@ -1,0 +1,54 @@
+// Library-internal objects behind the opaque handles of plss.h.
+#pragma once
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/plss.h"
+#include "common.hpp"
+#include "kernels.hpp"
+
+// One direction of the matrix store: CSR of A, or CSR of Aᵀ (= CSC of A).
+struct PlssDir {
+  int nrows = 0, ncols = 0;
+  int* ptr = nullptr;    // nrows + 1
+  int* idx = nullptr;    // nnz
+  void* val = nullptr;   // nnz, f64 or f32
+  int* tile = nullptr;   // ntiles + 1
+  int ntiles = 0;
+  int V = 8;             // entries per thread of a tile (tile = 256*V entries)
+  std::vector<int> h_ptr;  // host copy of ptr (tile construction)
+};
+
+struct plss_handle {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::mutex mu;
+  double kt_ms[4] = {0, 0, 0, 0};
+  long long kt_n[4] = {0, 0, 0, 0};
+};
+
+struct plss_matrix {
+  plss_handle* h = nullptr;
+  long long m = 0, n = 0, nnz = 0;
+  bool f32 = false;
+  PlssDir A, T;
+  size_t bytes = 0;
+};
+
+namespace plss {
+
+// device allocation that reports ENOMEM through an exception
+void* dmalloc(size_t bytes);
+void dfree(void* p);
+
+// tile table of a pointer array for tiles of 256*V entries
+std::vector<int> make_tiles(const std::vector<int>& ptr, int V);
+void set_tiles(PlssDir& d, int V, hipStream_t s);
+
+// validated store creation (throws InvalidArg / OutOfMemory / DeviceError)
+plss_matrix* matrix_create(plss_handle* h, const plss_csr* A, plss_dtype storage, hipStream_t s);
+void matrix_destroy(plss_matrix* A);
+size_t matrix_footprint(long long m, long long n, long long nnz, bool f32);
+
+}  // namespace plss

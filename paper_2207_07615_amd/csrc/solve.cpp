@@ -1,0 +1,332 @@
+// Iteration driver: one or many residual-sketch systems advanced together.
+//
+// Every launch walks a list of (system, tile) pairs; systems that finished
+// are dropped from the lists at the next host check.  Decisions of the
+// method (stop test, breakdown, refinement restarts) are taken on the device
+// by k_step / k_outer, so a chunk of iterations runs without host
+// round-trips; the host only reads the per-system State once per chunk.
+#include "solve.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+
+namespace plss {
+
+static size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
+
+void validate_opts(const plss_opts* o, bool f32) {
+  if (!o) throw InvalidArg{"null opts"};
+  if (!(o->tol > 0.0) || !std::isfinite(o->tol)) throw InvalidArg{"tol must be positive and finite"};
+  if (o->maxit <= 0) throw InvalidArg{"maxit must be positive"};
+  if (o->sketch < PLSS_SKETCH_RESIDUAL || o->sketch > PLSS_SKETCH_MIXED)
+    throw InvalidArg{"unknown sketch"};
+  if (f32 && o->refine && (!(o->inner_tol > 0.0) || !(o->inner_tol < 1.0)))
+    throw InvalidArg{"inner_tol must be in (0, 1)"};
+  if (f32 && o->refine && o->max_outer <= 0) throw InvalidArg{"max_outer must be positive"};
+  if (o->chunk < 0) throw InvalidArg{"chunk must be >= 0"};
+}
+
+SysRun::~SysRun() { dfree(arena); }
+
+void SysRun::setup(const plss_matrix* M, const double* b_in, const plss_opts* o, long long hist_len_in,
+                   State* d_state, Desc* desc_slot_unused) {
+  (void)desc_slot_unused;
+  A = M;
+  f32 = M->f32;
+  const size_t m = M->m, n = M->n;
+  const size_t vs = f32 ? 4 : 8;
+  u_nblk = (int)((n + 1023) / 1024);
+  hist_len = std::max<long long>(1, hist_len_in);
+  // arena layout
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o2 = off;
+    off = align_up(off + bytes);
+    return o2;
+  };
+  const size_t o_b = take(8 * m), o_xo = take(8 * n), o_x = f32 ? take(8 * n) : 0, o_r64 = take(8 * m);
+  const size_t o_r = take(vs * m), o_p = take(vs * n), o_y = take(vs * n), o_c = f32 ? take(vs * m) : 0;
+  const size_t o_wi = o->wi_diag ? take(8 * n) : 0;
+  const size_t o_pr = take(8 * M->A.ntiles), o_pb = take(8 * M->A.ntiles);
+  const size_t o_pp = take(8 * M->T.ntiles), o_pt = take(8 * u_nblk);
+  const size_t o_h = take(8 * (size_t)hist_len);
+  arena = static_cast<char*>(dmalloc(off));
+  bytes = off;
+  std::memset(&desc, 0, sizeof(desc));
+  desc.a_ptr = M->A.ptr;
+  desc.a_idx = M->A.idx;
+  desc.a_val = M->A.val;
+  desc.a_tile = M->A.tile;
+  desc.a_ntiles = M->A.ntiles;
+  desc.t_ptr = M->T.ptr;
+  desc.t_idx = M->T.idx;
+  desc.t_val = M->T.val;
+  desc.t_tile = M->T.tile;
+  desc.t_ntiles = M->T.ntiles;
+  desc.m = (int)m;
+  desc.n = (int)n;
+  desc.u_nblk = u_nblk;
+  desc.b = reinterpret_cast<double*>(arena + o_b);
+  desc.xo = reinterpret_cast<double*>(arena + o_xo);
+  desc.x = f32 ? reinterpret_cast<double*>(arena + o_x) : desc.xo;
+  desc.r64 = reinterpret_cast<double*>(arena + o_r64);
+  desc.r = arena + o_r;
+  desc.p = arena + o_p;
+  desc.y = arena + o_y;
+  desc.c = f32 ? arena + o_c : nullptr;
+  desc.wi = o->wi_diag ? reinterpret_cast<double*>(arena + o_wi) : nullptr;
+  desc.part_rho = reinterpret_cast<double*>(arena + o_pr);
+  desc.part_b = reinterpret_cast<double*>(arena + o_pb);
+  desc.part_phi = reinterpret_cast<double*>(arena + o_pp);
+  desc.part_theta = reinterpret_cast<double*>(arena + o_pt);
+  desc.hist = reinterpret_cast<double*>(arena + o_h);
+  desc.hist_len = hist_len;
+  desc.st = d_state;
+  desc.is_f32 = f32;
+
+  std::memset(&st0, 0, sizeof(st0));
+  st0.done = 1;  // the outer step runs first: r64 = b - A x0, then the inner start
+  st0.final_done = 0;
+  st0.tol = o->tol;
+  st0.tol_out = o->tol;
+  st0.tol_abs = o->tol_absolute ? 1 : 0;
+  st0.inner_tol = f32 && o->refine ? o->inner_tol : o->tol;
+  st0.maxit = o->maxit;
+  st0.max_outer = f32 && o->refine ? o->max_outer : 1;
+  st0.status = ST_OK;
+  st0.nu = f32 ? INFINITY : 1.0;
+}
+
+void SysRun::upload(const double* b_in, const double* x0, const double* wi, hipStream_t s) {
+  const size_t m = A->m, n = A->n;
+  PLSS_HIP(hipMemcpyAsync(const_cast<double*>(desc.b), b_in, 8 * m, hipMemcpyDefault, s));
+  if (x0) PLSS_HIP(hipMemcpyAsync(desc.xo, x0, 8 * n, hipMemcpyDefault, s));
+  else PLSS_HIP(hipMemsetAsync(desc.xo, 0, 8 * n, s));
+  if (f32) PLSS_HIP(hipMemsetAsync(desc.x, 0, 8 * n, s));
+  if (wi) PLSS_HIP(hipMemcpyAsync(const_cast<double*>(desc.wi), static_cast<const void*>(wi), 8 * n, hipMemcpyDefault, s));
+}
+
+// ------------------------------------------------------------------ batch runner
+
+namespace {
+
+struct Lists {
+  // key: (f32, V) for tile lists, f32 for block lists
+  std::map<int, std::vector<int2>> a, t, u;
+  std::vector<int> s;
+  std::map<int, std::vector<int2>> a_f;  // CSR tiles grouped by f32 only (start kernel)
+};
+
+struct DevLists {
+  std::vector<std::pair<int, std::pair<const int2*, int>>> a, t, u, af;
+  const int* s = nullptr;
+  int ns = 0;
+};
+
+}  // namespace
+
+BatchRunner::BatchRunner(plss_handle* h) : h_(h) {}
+
+BatchRunner::~BatchRunner() {
+  dfree(d_desc_);
+  dfree(d_state_);
+  dfree(d_lists_);
+  if (h_state_) (void)hipHostFree(h_state_);
+  if (h_lists_) (void)hipHostFree(h_lists_);
+  for (auto e : events_) (void)hipEventDestroy(e);
+}
+
+void BatchRunner::add(const plss_matrix* A, const double* b, const plss_opts* o, long long hist_len) {
+  validate_opts(o, A->f32);
+  if (o->sketch != PLSS_SKETCH_RESIDUAL) throw InvalidArg{"batched solves use the residual sketch"};
+  if (o->wi_diag && o->sketch != PLSS_SKETCH_RESIDUAL) throw InvalidArg{"wi_diag needs the residual sketch"};
+  Item it;
+  it.A = A;
+  it.b = b;
+  it.o = *o;
+  it.hist_len = hist_len;
+  items_.push_back(it);
+}
+
+void BatchRunner::prepare(hipStream_t s) {
+  const int ns = (int)items_.size();
+  d_state_ = static_cast<State*>(dmalloc(sizeof(State) * ns));
+  d_desc_ = static_cast<Desc*>(dmalloc(sizeof(Desc) * ns));
+  PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_state_), sizeof(State) * ns, hipHostMallocDefault));
+  runs_.resize(ns);
+  std::vector<Desc> descs(ns);
+  std::vector<State> st(ns);
+  for (int i = 0; i < ns; ++i) {
+    Item& it = items_[i];
+    runs_[i].reset(new SysRun());
+    SysRun& r = *runs_[i];
+    r.setup(it.A, it.b, &it.o, it.hist_len, d_state_ + i, nullptr);
+    r.upload(it.b, it.o.x0, it.o.wi_diag, s);
+    descs[i] = r.desc;
+    st[i] = r.st0;
+  }
+  PLSS_HIP(hipMemcpyAsync(d_desc_, descs.data(), sizeof(Desc) * ns, hipMemcpyHostToDevice, s));
+  PLSS_HIP(hipMemcpyAsync(d_state_, st.data(), sizeof(State) * ns, hipMemcpyHostToDevice, s));
+  // finite check of b (and x0 / wi) on the device
+  PLSS_HIP(hipStreamSynchronize(s));
+  std::memcpy(h_state_, st.data(), sizeof(State) * ns);
+}
+
+void BatchRunner::build_lists(const std::vector<int>& active, hipStream_t s) {
+  std::map<int, std::vector<int2>> la, lt, lu, laf;
+  std::vector<int> ls;
+  for (int i : active) {
+    const SysRun& r = *runs_[i];
+    const int f = r.f32 ? 1 : 0;
+    auto& A = la[f * 100 + r.A->A.V];
+    for (int t = 0; t < r.A->A.ntiles; ++t) A.push_back(make_int2(i, t));
+    auto& AF = laf[f];
+    for (int t = 0; t < r.A->A.ntiles; ++t) AF.push_back(make_int2(i, t));
+    auto& T = lt[f * 100 + r.A->T.V];
+    for (int t = 0; t < r.A->T.ntiles; ++t) T.push_back(make_int2(i, t));
+    auto& U = lu[f];
+    for (int t = 0; t < r.u_nblk; ++t) U.push_back(make_int2(i, t));
+    ls.push_back(i);
+  }
+  size_t total = ls.size() * sizeof(int) + 64;
+  for (auto* mp : {&la, &lt, &lu, &laf})
+    for (auto& kv : *mp) total += kv.second.size() * sizeof(int2) + 64;
+  if (total > lists_cap_) {
+    dfree(d_lists_);
+    if (h_lists_) (void)hipHostFree(h_lists_);
+    lists_cap_ = total * 2;
+    d_lists_ = static_cast<char*>(dmalloc(lists_cap_));
+    PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_lists_), lists_cap_, hipHostMallocDefault));
+  }
+  size_t off = 0;
+  groups_a_.clear();
+  groups_t_.clear();
+  groups_u_.clear();
+  groups_af_.clear();
+  auto put = [&](std::map<int, std::vector<int2>>& mp, std::vector<Group>& out) {
+    for (auto& kv : mp) {
+      if (kv.second.empty()) continue;
+      std::memcpy(h_lists_ + off, kv.second.data(), kv.second.size() * sizeof(int2));
+      Group g;
+      g.key = kv.first;
+      g.list = reinterpret_cast<const int2*>(d_lists_ + off);
+      g.n = (int)kv.second.size();
+      out.push_back(g);
+      off = align_up(off + kv.second.size() * sizeof(int2), 64);
+    }
+  };
+  put(la, groups_a_);
+  put(lt, groups_t_);
+  put(lu, groups_u_);
+  put(laf, groups_af_);
+  std::memcpy(h_lists_ + off, ls.data(), ls.size() * sizeof(int));
+  d_sys_ = reinterpret_cast<const int*>(d_lists_ + off);
+  n_sys_ = (int)ls.size();
+  off += ls.size() * sizeof(int);
+  PLSS_HIP(hipMemcpyAsync(d_lists_, h_lists_, off, hipMemcpyHostToDevice, s));
+}
+
+void BatchRunner::outer_seq(hipStream_t s) {
+  for (auto& g : groups_u_) launch_axpy_out(d_desc_, g.list, g.n, s);
+  for (auto& g : groups_a_) launch_spmv(MODE_REFINE, g.key >= 100, g.key % 100, d_desc_, g.list, g.n, 0, s);
+  launch_outer(d_desc_, d_sys_, n_sys_, s);
+  for (auto& g : groups_af_) launch_start(g.key == 1, d_desc_, g.list, g.n, s);
+}
+
+void BatchRunner::iteration(hipStream_t s, hipEvent_t* ev) {
+  if (ev) PLSS_HIP(hipEventRecord(ev[0], s));
+  for (auto& g : groups_a_) launch_spmv(MODE_RESID, g.key >= 100, g.key % 100, d_desc_, g.list, g.n, 0, s);
+  if (ev) PLSS_HIP(hipEventRecord(ev[1], s));
+  for (auto& g : groups_t_) launch_spmv(MODE_TRANS, g.key >= 100, g.key % 100, d_desc_, g.list, g.n, 1, s);
+  if (ev) PLSS_HIP(hipEventRecord(ev[2], s));
+  launch_step(d_desc_, d_sys_, n_sys_, s);
+  if (ev) PLSS_HIP(hipEventRecord(ev[3], s));
+  for (auto& g : groups_u_) launch_update(g.key == 1, d_desc_, g.list, g.n, s);
+  if (ev) PLSS_HIP(hipEventRecord(ev[4], s));
+}
+
+void BatchRunner::run(hipStream_t s, bool timing, int chunk_req) {
+  const int ns = (int)items_.size();
+  std::vector<int> active;
+  for (int i = 0; i < ns; ++i) active.push_back(i);
+  build_lists(active, s);
+  bool any_f32 = false;
+  double bytes_iter = 0;
+  for (int i = 0; i < ns; ++i) {
+    any_f32 |= runs_[i]->f32;
+    const plss_matrix* M = runs_[i]->A;
+    bytes_iter += (M->f32 ? 16.0 : 24.0) * M->nnz + 28.0 * M->m + 60.0 * M->n;
+  }
+  // iterations per chunk: grow from a small first chunk (small systems finish
+  // early) towards ~4 ms of work between host checks
+  const double t_iter = bytes_iter / 4.0e12 + 20e-6;
+  int cmax = (int)std::min(128.0, std::max(8.0, 4e-3 / t_iter));
+  int chunk = chunk_req > 0 ? chunk_req : std::min(16, cmax);
+  const int outer_every = any_f32 ? 4 : 1 << 30;
+  if (timing && events_.empty()) {
+    events_.resize(5 * 128);
+    for (auto& e : events_) PLSS_HIP(hipEventCreate(&e));
+  }
+  hipEvent_t t0, t1;
+  PLSS_HIP(hipEventCreate(&t0));
+  PLSS_HIP(hipEventCreate(&t1));
+  PLSS_HIP(hipEventRecord(t0, s));
+  while (!active.empty()) {
+    outer_seq(s);
+    const int c = timing ? std::min(chunk, 128) : chunk;
+    for (int it = 0; it < c; ++it) {
+      if (it > 0 && it % outer_every == 0) outer_seq(s);
+      iteration(s, timing ? &events_[5 * it] : nullptr);
+    }
+    outer_seq(s);
+    PLSS_HIP(hipMemcpyAsync(h_state_, d_state_, sizeof(State) * ns, hipMemcpyDeviceToHost, s));
+    PLSS_HIP(hipStreamSynchronize(s));
+    if (timing) {
+      for (int it = 0; it < c; ++it) {
+        for (int q = 0; q < 4; ++q) {
+          float ms = 0;
+          PLSS_HIP(hipEventElapsedTime(&ms, events_[5 * it + q], events_[5 * it + q + 1]));
+          h_->kt_ms[q] += ms;
+          h_->kt_n[q] += 1;
+        }
+      }
+    }
+    std::vector<int> still;
+    for (int i : active)
+      if (!h_state_[i].final_done) still.push_back(i);
+    if (still.size() != active.size()) {
+      active.swap(still);
+      if (!active.empty()) build_lists(active, s);
+    }
+    if (chunk_req <= 0) chunk = std::min(cmax, chunk * 2);
+  }
+  PLSS_HIP(hipEventRecord(t1, s));
+  PLSS_HIP(hipEventSynchronize(t1));
+  float ms = 0;
+  PLSS_HIP(hipEventElapsedTime(&ms, t0, t1));
+  elapsed_ms_ = ms;
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+}
+
+void BatchRunner::result(int i, double* x, double* hist, long long hist_cap, plss_info* info,
+                         hipStream_t s) {
+  const SysRun& r = *runs_[i];
+  const State& st = h_state_[i];
+  if (x) PLSS_HIP(hipMemcpyAsync(x, r.desc.xo, 8 * (size_t)r.A->n, hipMemcpyDefault, s));
+  const long long nh = std::min<long long>({hist_cap, st.k_total + 1, r.hist_len});
+  if (hist && nh > 0) PLSS_HIP(hipMemcpyAsync(hist, r.desc.hist, 8 * nh, hipMemcpyDefault, s));
+  PLSS_HIP(hipStreamSynchronize(s));
+  if (info) {
+    info->iters = st.k_total;
+    info->outer_iters = st.outer;
+    info->relres = sqrt(st.rho) * st.scale;
+    info->relres_true = st.relres_true;
+    info->status = st.final_status;
+    info->ms = elapsed_ms_;
+  }
+}
+
+}  // namespace plss
