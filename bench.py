@@ -1,0 +1,203 @@
+#!/usr/bin/env python3
+"""PLSS benchmark on one MI355X.
+
+Workload (default): the large consistent system, 2,000,000 x 500,000, row
+lengths Zipf(1.5) clipped to [2, 2000] (nnz ~1.37e8), N(0,1) values,
+x* ~ N(0,1), b = A x*, residual sketch (Algorithm 1), FP64, relative
+tolerance 1e-8, maxit 1000.  One step = one full solve; A, b and x stay
+resident in HBM (torch device tensors) during the timed region.
+
+Reported: PLSS iterations/s (value), solves/s, algorithmic HBM GB/s of the
+iteration, the roofline of the dominant kernel (per-kernel HIP events on
+the library's stream during the timed region), the oracle timed on the host
+on a bounded sample, and the float32-storage + float64-refinement arm of the
+same system (timed separately after the main region).
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("PLSS iters/s & HBM GB/s (SpMV+SpMVᵀ); solves/s, p50/p99 at rel. res 1e-8")
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def bytes_model(m, n, nnz, f32=False):
+    """Algorithmic bytes per iteration and per kernel (int32 pointers and
+    indices; float64 vectors, or float32 vectors for float32 storage):
+      product with A  : v*nnz + 4*nnz + 4m (ptr) + 2w*m (r read+write) + w*n (p)
+      product with Aᵀ : v*nnz + 4*nnz + 4n (ptr) + w*n (y write) + w*m (r)
+      update          : 5w*n (p read+write, y read, x read+write; x in f64)"""
+    v = 4 if f32 else 8
+    w = 4 if f32 else 8
+    spmv = (v + 4) * nnz + 4 * m + 2 * w * m + w * n
+    spmvt = (v + 4) * nnz + 4 * n + w * n + w * m
+    upd = 3 * w * n + 16 * n
+    return {"spmv": spmv, "spmvt": spmvt, "update": upd, "iter": spmv + spmvt + upd}
+
+
+def cpu_baseline(sysm, iters=12):
+    """The oracle (Algorithm 1 in float64, SciPy sparse products) on the
+    first `iters` iterations of the same system, single-threaded."""
+    try:
+        from threadpoolctl import threadpool_limits
+        lim = threadpool_limits(1)
+    except Exception:
+        lim = None
+    from oracle import plss as O
+    t0 = time.perf_counter()
+    res = O.plss_residual(sysm.A, sysm.b, tol=1e-300, maxit=iters)
+    dt = time.perf_counter() - t0
+    if lim is not None:
+        lim.unregister() if hasattr(lim, "unregister") else None
+    return {"value": res.iters / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {res.iters} iterations of the same float64 solve "
+                      f"({dt:.1f} s, SciPy CSR products, 1 thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--m", type=int, default=2_000_000)
+    ap.add_argument("--n", type=int, default=500_000)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the float32 + refinement arm")
+    ap.add_argument("--autotune", action="store_true", help="pick tile widths by measurement")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2207_07615_amd as plss
+    import plss_inputs as gen
+
+    t0 = time.perf_counter()
+    sysm = gen.large(m=args.m, n=args.n)
+    A = sysm.A
+    log(f"generated m={A.m} n={A.n} nnz={A.nnz} in {time.perf_counter() - t0:.1f}s")
+
+    dev = torch.device("cuda:0")
+    h = plss.Handle(0)
+    t0 = time.perf_counter()
+    M = plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n))
+    log(f"device store (upload + CSC) in {time.perf_counter() - t0:.2f}s")
+    if args.autotune:
+        log(f"tile widths {M.autotune()}")
+    b = torch.from_numpy(sysm.b).to(dev)
+    torch.cuda.synchronize()
+
+    kw = dict(tol=1e-8, maxit=1000)
+    for _ in range(args.warmup):
+        plss.solve(h, M, b, **kw)
+    plss.kernel_times(h)  # reset
+    torch.cuda.synchronize()
+    lat, iters = [], []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        x, info, _ = plss.solve(h, M, b, timing=True, **kw)
+        lat.append(time.perf_counter() - ts)
+        iters.append(info["iters"])
+        assert info["status"] == 0, info
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    kms, kn = plss.kernel_times(h)
+    relres_true = info["relres_true"]
+    err_xstar = float(torch.linalg.norm(x - torch.from_numpy(sysm.xstar).to(dev)) /
+                      np.linalg.norm(sysm.xstar))
+
+    bm = bytes_model(A.m, A.n, A.nnz)
+    tot_iters = sum(iters)
+    iters_per_s = tot_iters / wall
+    avg = [kms[q] / max(1, kn[q]) for q in range(4)]
+    dom = 0 if avg[0] >= avg[1] else 1
+    dom_bytes = bm["spmv"] if dom == 0 else bm["spmvt"]
+    achieved = dom_bytes / (avg[dom] * 1e-3) / 1e9
+    pair_gbs = (bm["spmv"] + bm["spmvt"]) / ((avg[0] + avg[1]) * 1e-3) / 1e9
+    lat_ms = sorted(1e3 * v for v in lat)
+
+    out = {
+        "metric": METRIC,
+        "value": iters_per_s,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded; stands in for the paper's SuiteSparse matrices)",
+        "config": {"workload": "large: 2,000,000 x 500,000 CSR, Zipf(1.5) rows clipped to [2,2000], "
+                               "N(0,1), residual sketch, FP64, rel. tol 1e-8",
+                   "m": A.m, "n": A.n, "nnz": A.nnz, "tol": 1e-8, "maxit": 1000},
+        "iters_per_solve": tot_iters / args.steps,
+        "solves_per_s": args.steps / wall,
+        "p50_ms": lat_ms[len(lat_ms) // 2],
+        "p99_ms": lat_ms[min(len(lat_ms) - 1, int(math.ceil(0.99 * len(lat_ms))) - 1)],
+        "hbm_gbps_iteration": bm["iter"] * iters_per_s / 1e9,
+        "hbm_gbps_spmv_pair": pair_gbs,
+        "kernel_ms": {"spmv": avg[0], "spmvt": avg[1], "step": avg[2], "update": avg[3]},
+        "relres_true": relres_true,
+        "rel_err_vs_xstar": err_xstar,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "spmv (r -= A p, rho)" if dom == 0 else "spmvt (y = A^T r, phi)",
+                     "algorithmic_bytes_per_launch": dom_bytes},
+    }
+
+    if not args.no_fp32:
+        A32 = A.astype(np.float32)
+        b32 = torch.from_numpy(gen.rhs(A32, sysm.xstar)).to(dev)
+        M32 = plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n), storage="f32")
+        if args.autotune:
+            M32.autotune()
+        kw32 = dict(tol=1e-8, maxit=4000, refine=True, inner_tol=1e-4, max_outer=20)
+        plss.solve(h, M32, b32, **kw32)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        n32 = max(1, args.steps // 2)
+        its32 = []
+        for _ in range(n32):
+            x32, i32, _ = plss.solve(h, M32, b32, **kw32)
+            its32.append(i32["iters"])
+        torch.cuda.synchronize()
+        w32 = time.perf_counter() - t1
+        out["fp32_refine"] = {
+            "solves_per_s": n32 / w32, "ms_per_solve": 1e3 * w32 / n32,
+            "iters_per_solve": sum(its32) / n32, "outer_iters": i32["outer_iters"],
+            "relres_true": i32["relres_true"], "status": i32["status_name"],
+            "speedup_vs_fp64_solves": (n32 / w32) / (args.steps / wall),
+            "iters_per_s": sum(its32) / w32,
+            "hbm_gbps_iteration": bytes_model(A.m, A.n, A.nnz, True)["iter"] * sum(its32) / w32 / 1e9,
+        }
+        del M32
+
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(sysm)
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

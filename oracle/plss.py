@@ -82,11 +82,14 @@ def _relres_true(S, x, b, nb):
 
 
 def plss_residual(A, b, tol=1e-8, maxit=1000, x0=None, wi=None, tol_absolute=False,
-                  record=False) -> Result:
+                  record=False, dot=None) -> Result:
     """Algorithm 1 (PLSS) with residual sketch S_k = [r_0 ... r_{k-1}] (eq. S).
 
     ``wi`` is the diagonal of the optional parameter matrix BᵀB (the inverse of
-    W); None means W = I."""
+    W); None means W = I.  ``dot`` replaces the inner product (default
+    ``numpy.dot``): runs that differ only in its summation order measure how
+    far two equally valid float64 evaluations of Algorithm 1 drift apart."""
+    dot = dot or (lambda a, c: float(a @ c))
     S = _as_sparse(A)
     m, n = S.shape
     b = np.asarray(b, dtype=np.float64)
@@ -98,7 +101,7 @@ def plss_residual(A, b, tol=1e-8, maxit=1000, x0=None, wi=None, tol_absolute=Fal
     # Initialisation (Algorithm 1, before the loop)
     x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64)
     r = b - S @ x
-    rho = float(r @ r)
+    rho = dot(r, r)
     hist = [math.sqrt(rho) * scale]
     xs = [x.copy()] if record else None
     ps = [] if record else None
@@ -111,11 +114,11 @@ def plss_residual(A, b, tol=1e-8, maxit=1000, x0=None, wi=None, tol_absolute=Fal
         return done(OK, 0)
     y = S.T @ r
     WIy = y / WI
-    phi = float(y @ WIy)
+    phi = dot(y, WIy)
     if not (phi > 0.0):
         return done(BREAKDOWN, 0)
     p = (rho / phi) * WIy
-    theta = float(p @ (WI * p))
+    theta = dot(p, WI * p)
     x = x + p
     k = 1
     if record:
@@ -123,7 +126,7 @@ def plss_residual(A, b, tol=1e-8, maxit=1000, x0=None, wi=None, tol_absolute=Fal
 
     while True:
         r = r - S @ p
-        rho = float(r @ r)
+        rho = dot(r, r)
         hist.append(math.sqrt(rho) * scale)
         if record:
             rs.append(r.copy())
@@ -133,14 +136,14 @@ def plss_residual(A, b, tol=1e-8, maxit=1000, x0=None, wi=None, tol_absolute=Fal
             return done(NOT_CONVERGED, k)
         y = S.T @ r
         WIy = y / WI
-        phi = float(y @ WIy)
+        phi = dot(y, WIy)
         s = math.sqrt(theta * phi) / rho
         if not (s > 1.0):
             return done(BREAKDOWN, k)
         beta = 1.0 / ((s - 1.0) * (s + 1.0))
         gamma = (theta / rho) * beta
         p = beta * p + gamma * WIy
-        theta = float(p @ (WI * p))
+        theta = dot(p, WI * p)
         x = x + p
         k += 1
         if record:

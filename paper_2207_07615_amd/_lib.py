@@ -66,9 +66,20 @@ EXPORTS = {
 _lib = None
 
 
+def _single_runtime():
+    """PyTorch ships its own HIP runtime (same SONAME as ROCm's).  Importing
+    torch before libplss.so makes the library bind to that runtime, so torch
+    device pointers and library pointers live in one runtime; loading
+    libplss.so first would map a second runtime once torch is imported."""
+    import importlib.util
+    if importlib.util.find_spec("torch") is not None:
+        import torch  # noqa: F401
+
+
 def load() -> C.CDLL:
     global _lib
     if _lib is None:
+        _single_runtime()
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2207_07615_amd.build`")

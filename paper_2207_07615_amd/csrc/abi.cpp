@@ -101,11 +101,11 @@ plss_status plss_create(plss_handle** out, int device) {
 }
 
 plss_status plss_destroy(plss_handle* h) {
-  if (!h) return PLSS_EINVAL;
+  if (!h || h->closed) return PLSS_EINVAL;
   DeviceScope ds(h->device);
-  (void)hipStreamSynchronize(h->stream);
-  (void)hipStreamDestroy(h->stream);
-  delete h;
+  h->closed = true;
+  h->refs += 1;
+  handle_release(h);  // frees now unless matrices or servers still use it
   return PLSS_OK;
 }
 
@@ -113,6 +113,7 @@ plss_status plss_matrix_create(plss_handle* h, const plss_csr* A, plss_dtype sto
                                plss_matrix** out) {
   PLSS_GUARD_BEGIN
   if (!h || !out) throw InvalidArg{"null handle or output"};
+  if (h->closed) throw InvalidArg{"handle destroyed"};
   DeviceScope ds(h->device);
   std::lock_guard<std::mutex> lk(h->mu);
   *out = matrix_create(h, A, storage, h->stream);
@@ -122,9 +123,11 @@ plss_status plss_matrix_create(plss_handle* h, const plss_csr* A, plss_dtype sto
 
 plss_status plss_matrix_destroy(plss_matrix* A) {
   if (!A) return PLSS_EINVAL;
-  DeviceScope ds(A->h->device);
-  (void)hipStreamSynchronize(A->h->stream);
+  plss_handle* h = A->h;
+  DeviceScope ds(h->device);
+  (void)hipStreamSynchronize(h->stream);
   matrix_destroy(A);
+  handle_release(h);
   return PLSS_OK;
 }
 

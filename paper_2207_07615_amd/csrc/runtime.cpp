@@ -148,6 +148,7 @@ plss_matrix* matrix_create(plss_handle* h, const plss_csr* A, plss_dtype storage
   dfree(d_rp64);
   dfree(dflag);
   dfree(work);
+  h->refs += 1;
   M->bytes = (size_t)nnz * (vsz + 4) * 2 + sizeof(int) * (size_t)(m + n + 2) +
              sizeof(int) * (size_t)(M->A.ntiles + M->T.ntiles + 2);
   return M;
@@ -162,6 +163,16 @@ void matrix_destroy(plss_matrix* M) {
     dfree(d->tile);
   }
   delete M;
+}
+
+void handle_release(plss_handle* h) {
+  if (!h) return;
+  h->refs -= 1;
+  if (h->closed && h->refs <= 0) {
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipStreamDestroy(h->stream);
+    delete h;
+  }
 }
 
 }  // namespace plss

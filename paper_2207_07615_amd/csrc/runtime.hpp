@@ -24,6 +24,10 @@ struct plss_handle {
   int device = 0;
   hipStream_t stream = nullptr;
   std::mutex mu;
+  // matrices and servers created on the handle keep it alive: plss_destroy
+  // only frees it once the last of them is destroyed
+  int refs = 0;
+  bool closed = false;
   double kt_ms[4] = {0, 0, 0, 0};
   long long kt_n[4] = {0, 0, 0, 0};
 };
@@ -49,6 +53,7 @@ void set_tiles(PlssDir& d, int V, hipStream_t s);
 // validated store creation (throws InvalidArg / OutOfMemory / DeviceError)
 plss_matrix* matrix_create(plss_handle* h, const plss_csr* A, plss_dtype storage, hipStream_t s);
 void matrix_destroy(plss_matrix* A);
+void handle_release(plss_handle* h);  // drop one reference; frees a closed handle at zero
 size_t matrix_footprint(long long m, long long n, long long nnz, bool f32);
 
 }  // namespace plss

@@ -20,3 +20,41 @@ def csr_from_dense(D):
     S = sp.csr_matrix(D)
     S.sort_indices()
     return S.indptr.astype(np.int64), S.indices.astype(np.int32), S.data.astype(np.float64)
+
+
+def fsum_dot(a, b):
+    import math
+    return math.fsum(a * b)
+
+
+def fp64_parity(h, sysm, tol=1e-8, maxit=5000, wi=None, storage="f64"):
+    """Check a float64 solve against Algorithm 1 (oracle):
+
+    * the GPU meets the stop test and its iteration count is within one of
+      the oracle's own count;
+    * at the GPU's iteration count the two iterates agree within
+      max(1e-10, 4 x the spread between two equally valid float64 runs of the
+      oracle that differ only in the summation order of inner products);
+      the finite-precision Craig/Lanczos process amplifies rounding
+      differences, so this spread (not machine epsilon) is the floor;
+    * the first 15 iterates agree to 1e-12 (before the amplification).
+    Returns the GPU's (x, info)."""
+    import paper_2207_07615_amd as plss
+    from oracle import plss as O
+    M = matrix(h, sysm.A, storage)
+    x, info, hist = plss.solve(h, M, sysm.b, tol=tol, maxit=maxit, wi=wi)
+    assert info["status"] == 0, info
+    k = info["iters"]
+    ref = O.plss_residual(sysm.A, sysm.b, tol=1e-300, maxit=k, wi=wi)
+    alt = O.plss_residual(sysm.A, sysm.b, tol=1e-300, maxit=k, wi=wi, dot=fsum_dot)
+    floor = rel(alt.x, ref.x)
+    err = rel(x, ref.x)
+    print(f"  iters={k} err_vs_oracle={err:.3e} oracle_order_spread={floor:.3e}", flush=True)
+    assert err <= max(1e-10, 4 * floor)
+    full = O.plss_residual(sysm.A, sysm.b, tol=tol, maxit=maxit, wi=wi)
+    assert abs(full.iters - k) <= 1
+    k15 = min(15, k)
+    x15, i15, _ = plss.solve(h, M, sysm.b, tol=1e-300, maxit=k15, wi=wi)
+    r15 = O.plss_residual(sysm.A, sysm.b, tol=1e-300, maxit=k15, wi=wi)
+    assert rel(x15, r15.x) <= 1e-12
+    return x, info, M

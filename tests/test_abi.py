@@ -27,7 +27,8 @@ def test_header_declares_entry_points():
 def test_library_exports_every_declared_symbol():
     if not os.path.exists(LIB):
         pytest.fail("libplss.so is not built (python -m paper_2207_07615_amd.build)")
-    lib = ctypes.CDLL(LIB)
+    from paper_2207_07615_amd import _lib as L
+    lib = L.load()
     missing = [n for n in declared() if not hasattr(lib, n)]
     assert not missing, missing
 
