@@ -236,7 +236,8 @@ __global__ __launch_bounds__(kWG) void k_axpy_out(const Desc* __restrict__ D,
   const int2 ent = list[blockIdx.x];
   const Desc* d = D + ent.x;
   const State* st = d->st;
-  if (st->final_done || !st->done || !d->is_f32) return;
+  // only after an inner solve (outer >= 1): nu and d are defined from then on
+  if (st->final_done || !st->done || !d->is_f32 || st->outer == 0) return;
   const double nu = st->nu;
   const int base = ent.y * (kWG * 4);
   for (int u = 0; u < 4; ++u) {

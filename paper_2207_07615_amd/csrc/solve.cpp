@@ -96,7 +96,7 @@ void SysRun::setup(const plss_matrix* M, const double* b_in, const plss_opts* o,
   st0.maxit = o->maxit;
   st0.max_outer = f32 && o->refine ? o->max_outer : 1;
   st0.status = ST_OK;
-  st0.nu = f32 ? INFINITY : 1.0;
+  st0.nu = f32 ? 0.0 : 1.0;  // set by the outer step before any use
 }
 
 void SysRun::upload(const double* b_in, const double* x0, const double* wi, hipStream_t s) {
