@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 + refinement arm")
     ap.add_argument("--autotune", action="store_true", help="pick tile widths by measurement")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a 1 GiB device copy (calibrates profiler byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -122,6 +124,12 @@ def main():
     wall = time.perf_counter() - t_start
     kms, kn = plss.kernel_times(h)
     relres_true = info["relres_true"]
+    if args.calib_copy:
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        for _ in range(2):
+            dst = src.clone()
+        torch.cuda.synchronize()
+        del src, dst
     err_xstar = float(torch.linalg.norm(x - torch.from_numpy(sysm.xstar).to(dev)) /
                       np.linalg.norm(sysm.xstar))
 

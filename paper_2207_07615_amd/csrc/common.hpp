@@ -3,9 +3,11 @@
 // Device-side layout:
 //  * A is held twice: CSR (rows of A) and CSC (rows of Aᵀ), int32 pointers
 //    and indices, values in float64 or float32 storage.
-//  * Each direction carries a tile table: tile t covers rows
-//    [tile[t], tile[t+1]) with at most kTileNnz(V) stored entries and at most
-//    that many rows, or exactly one row when that row alone is longer.
+//  * Each direction carries a table of wave tiles: tile t covers rows
+//    [tile[t], tile[t+1]) with at most 64*V stored entries and at most that
+//    many rows, or exactly one row when that row alone is longer.  Four
+//    wave tiles of similar cost form a group, the unit of one workgroup:
+//    long-row tiles are grouped by length, short tiles in row order.
 //  * Per system, a Desc (plain pointers) and a State (scalars of the
 //    iteration) live in device memory; a launch of any phase kernel walks a
 //    list of (system, tile) pairs, so one launch serves one system or many.
@@ -71,13 +73,17 @@ struct Desc {
   const int* a_ptr;
   const int* a_idx;
   const void* a_val;
-  const int* a_tile;
-  int a_ntiles;
+  const int* a_tile;           // row start of every wave tile (a_nwt + 1)
+  const int* a_grp;            // 4 wave tiles per group (-1 = none), a_ntiles groups
+  int a_nwt;                   // wave tiles
+  int a_ntiles;                // groups of 4 wave tiles (one workgroup, one partial each)
   // CSC of A (= CSR of Aᵀ)
   const int* t_ptr;
   const int* t_idx;
   const void* t_val;
   const int* t_tile;
+  const int* t_grp;
+  int t_nwt;
   int t_ntiles;
   int m, n;
   int u_nblk;                  // blocks of the vector-update kernel
@@ -112,7 +118,7 @@ struct Desc {
   int is_f32;
 };
 
-inline int tile_nnz(int V) { return kWG * V; }
+inline int tile_nnz(int V) { return 64 * V; }
 
 // thread-local error text of the C ABI
 void set_error(const std::string& s);

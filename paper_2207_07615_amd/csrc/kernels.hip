@@ -49,6 +49,29 @@ __device__ double block_sum_array(const double* __restrict__ a, int n, double* s
   return block_sum(v, s_tmp);
 }
 
+// Same with 1024 threads (16 waves), 4 independent loads per thread in flight.
+constexpr int kRW = 1024;
+__device__ double big_sum_array(const double* __restrict__ a, int n, double* s_tmp) {
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+  int i = threadIdx.x;
+  for (; i + 3 * kRW < n; i += 4 * kRW) {
+    v0 += a[i];
+    v1 += a[i + kRW];
+    v2 += a[i + 2 * kRW];
+    v3 += a[i + 3 * kRW];
+  }
+  for (; i < n; i += kRW) v0 += a[i];
+  double v = (v0 + v1) + (v2 + v3);
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) s_tmp[w] = v;
+  __syncthreads();
+  double t = s_tmp[0];
+  for (int q = 1; q < kRW / 64; ++q) t += s_tmp[q];
+  return t;
+}
+
 // Exclusive segmented scan across the workgroup of (f, v) pairs, where a
 // set flag starts a new segment after the element:
 //   incl_j = f_j ? v_j : incl_{j-1} + v_j,  result_j = incl_{j-1} (0 for j = 0).
@@ -94,27 +117,60 @@ __device__ __forceinline__ bool spmv_skip(const State* st) {
 
 // ------------------------------------------------------------------ tile SpMV
 
+// Wave-level segmented scan (exclusive) of (f, v) pairs over the 64 lanes,
+// with the same combine rule as seg_scan_excl.
+template <class T>
+__device__ __forceinline__ T wave_seg_scan_excl(int f, T v) {
+  const int lane = threadIdx.x & 63;
+  T sv = v;
+  int sf = f;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    T ov = __shfl_up(sv, off, 64);
+    int of = __shfl_up(sf, off, 64);
+    if (lane >= off) {
+      if (!sf) sv = ov + sv;
+      sf |= of;
+    }
+  }
+  T ex = __shfl_up(sv, 1, 64);
+  if (lane == 0) ex = T(0);
+  return ex;
+}
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One launch covers a list of (system, group) pairs; a group is 4
+// consecutive wave tiles of one system, one per wave of the workgroup.  A
+// wave tile holds at most 64*V stored entries and at most 64*V rows, or a
+// single longer row.  Short-row tiles stage products in wave-private LDS
+// and split them into rows with a segmented scan; long rows are summed in
+// registers by the whole wave.  Each wave's tile sum order and each group's
+// partial are fixed by the matrix alone.
 template <class Val, class Vin, class Acc, int MODE, int V>
 __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
                                               const int2* __restrict__ list, int transpose) {
-  constexpr int T = kWG * V;
-  __shared__ Acc s_prod[T];
-  __shared__ Acc s_row[T];
-  __shared__ int s_off[T + 1];
-  __shared__ Acc s_sv[kWaves];
-  __shared__ int s_sf[kWaves];
-  __shared__ double s_red[kWaves];
+  constexpr int TW = 64 * V;
+  __shared__ Acc s_prod[kWaves][TW];        // products, then row sums
+  __shared__ int s_off[kWaves][TW + 1];     // row offsets of the tile
+  __shared__ double s_wp[2][kWaves];
 
   const int2 ent = list[blockIdx.x];
   const Desc* d = D + ent.x;
   const State* st = d->st;
   if (spmv_skip<MODE>(st)) return;
 
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const bool tr = (MODE == MODE_TRANS) || (MODE == MODE_PLAIN && transpose);
   const int* __restrict__ ptr = tr ? d->t_ptr : d->a_ptr;
   const int* __restrict__ idx = tr ? d->t_idx : d->a_idx;
   const Val* __restrict__ val = static_cast<const Val*>(tr ? d->t_val : d->a_val);
   const int* __restrict__ tile = tr ? d->t_tile : d->a_tile;
+  const int* __restrict__ grp = tr ? d->t_grp : d->a_grp;
 
   const Vin* __restrict__ xin;
   if (MODE == MODE_RESID) xin = static_cast<const Vin*>(d->p);
@@ -122,11 +178,6 @@ __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
   else if (MODE == MODE_REFINE) xin = reinterpret_cast<const Vin*>(d->xo);
   else if (MODE == MODE_PLAIN) xin = static_cast<const Vin*>(d->p);
   else xin = reinterpret_cast<const Vin*>(d->P + (size_t)st->kh * d->n);
-
-  const int t = ent.y;
-  const int r0 = tile[t], r1 = tile[t + 1];
-  const int e0 = ptr[r0];
-  const int nr = r1 - r0, ne = ptr[r1] - e0;
 
   double part = 0.0, part2 = 0.0;
 
@@ -160,71 +211,116 @@ __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
     }
   };
 
-  if (ne > T) {
-    // one row longer than a tile: the whole workgroup strides over it
-    Acc acc = Acc(0);
-    for (int e = threadIdx.x; e < ne; e += kWG)
-      acc += Acc(__builtin_nontemporal_load(&val[e0 + e])) *
-             Acc(xin[__builtin_nontemporal_load(&idx[e0 + e])]);
-    acc = block_sum(acc, s_sv);
-    if (threadIdx.x == 0) epi(r0, acc);
-  } else {
-    for (int i = threadIdx.x; i <= nr; i += kWG) s_off[i] = ptr[r0 + i] - e0;
-    // phase 1: stream the tile's entries (coalesced), gather x, stage products
+  const int wt = grp[ent.y * kWaves + w];
+  if (wt >= 0) {
+    const int r0 = tile[wt], r1 = tile[wt + 1];
+    const int e0 = ptr[r0];
+    const int nr = r1 - r0, ne = ptr[r1] - e0;
+    if (ne > TW) {
+      // one long row: the wave strides over it, 8 entries per lane in flight
+      constexpr int U = 8;
+      Acc acc = Acc(0);
+      int e = lane;
+      for (; e + 64 * (U - 1) < ne; e += 64 * U) {
+        int c[U];
+        Val v[U];
 #pragma unroll
-    for (int u = 0; u < V; ++u) {
-      const int e = u * kWG + threadIdx.x;
-      if (e < ne)
-        s_prod[e] = Acc(__builtin_nontemporal_load(&val[e0 + e])) *
-                    Acc(xin[__builtin_nontemporal_load(&idx[e0 + e])]);
-    }
-    __syncthreads();
-    // phase 2: each thread sums V consecutive products, split at row ends
-    const int c0 = threadIdx.x * V;
-    Acc acc = Acc(0), first_val = Acc(0);
-    int first_row = -1, has_end = 0;
-    if (c0 < ne) {
-      const int c1 = min(c0 + V, ne);
-      int lo = 0, hi = nr;  // s_off[lo] <= c0 < s_off[hi]
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (s_off[mid] <= c0) lo = mid;
-        else hi = mid;
+        for (int u = 0; u < U; ++u) {
+          c[u] = __builtin_nontemporal_load(&idx[e0 + e + 64 * u]);
+          v[u] = __builtin_nontemporal_load(&val[e0 + e + 64 * u]);
+        }
+        Acc xv[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = Acc(xin[c[u]]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += Acc(v[u]) * xv[u];
       }
-      int rr = lo;
-      int rend = s_off[rr + 1];
-      for (int e = c0; e < c1; ++e) {
-        acc += s_prod[e];
-        if (e + 1 == rend) {
-          if (!has_end) {
-            first_row = rr;
-            first_val = acc;
-            has_end = 1;
-          } else {
-            s_row[rr] = acc;
+      for (; e < ne; e += 64)
+        acc += Acc(__builtin_nontemporal_load(&val[e0 + e])) *
+               Acc(xin[__builtin_nontemporal_load(&idx[e0 + e])]);
+      acc = wave_sum(acc);
+      if (lane == 0) epi(r0, acc);
+    } else {
+      Acc* sp = s_prod[w];
+      int* so = s_off[w];
+      for (int i = lane; i <= nr; i += 64) so[i] = ptr[r0 + i] - e0;
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        const int e = u * 64 + lane;
+        if (e < ne)
+          sp[e] = Acc(__builtin_nontemporal_load(&val[e0 + e])) *
+                  Acc(xin[__builtin_nontemporal_load(&idx[e0 + e])]);
+      }
+      wave_lds_sync();
+      // each lane sums V consecutive products, split at row ends
+      const int c0 = lane * V;
+      Acc acc = Acc(0);
+      Acc endv[V];
+      int endr[V];
+#pragma unroll
+      for (int q = 0; q < V; ++q) endr[q] = -1;
+      if (c0 < ne) {
+        int lo = 0, hi = nr;  // so[lo] <= c0 < so[hi]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (so[mid] <= c0) lo = mid;
+          else hi = mid;
+        }
+        int rr = lo;
+        int rend = so[rr + 1];
+#pragma unroll
+        for (int q = 0; q < V; ++q) {
+          const int e = c0 + q;
+          if (e < ne) {
+            acc += sp[e];
+            if (e + 1 == rend) {
+              endr[q] = rr;
+              endv[q] = acc;
+              acc = Acc(0);
+              ++rr;
+              while (rr < nr && so[rr + 1] == so[rr]) ++rr;
+              rend = (rr < nr) ? so[rr + 1] : INT_MAX;
+            }
           }
-          acc = Acc(0);
-          ++rr;
-          while (rr < nr && s_off[rr + 1] == s_off[rr]) ++rr;
-          rend = (rr < nr) ? s_off[rr + 1] : INT_MAX;
         }
       }
+      int has_end = 0;
+#pragma unroll
+      for (int q = 0; q < V; ++q) has_end |= (endr[q] >= 0);
+      const Acc carry = wave_seg_scan_excl<Acc>(has_end, acc);
+      wave_lds_sync();  // every lane has read its products: the buffer now takes row sums
+      bool first = true;
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        if (endr[q] >= 0) {
+          sp[endr[q]] = first ? endv[q] + carry : endv[q];
+          first = false;
+        }
+      }
+      wave_lds_sync();
+      for (int i = lane; i < nr; i += 64) epi(r0 + i, so[i] == so[i + 1] ? Acc(0) : sp[i]);
     }
-    const Acc carry = seg_scan_excl<Acc>(has_end, acc, s_sv, s_sf);
-    if (first_row >= 0) s_row[first_row] = first_val + carry;
-    for (int i = threadIdx.x; i < nr; i += kWG)
-      if (s_off[i] == s_off[i + 1]) s_row[i] = Acc(0);
-    __syncthreads();
-    for (int i = threadIdx.x; i < nr; i += kWG) epi(r0 + i, s_row[i]);
   }
 
   if (MODE == MODE_PLAIN) return;
-  part = block_sum(part, s_red);
-  if (MODE == MODE_REFINE) part2 = block_sum(part2, s_red);
+  part = wave_sum(part);
+  if (MODE == MODE_REFINE) part2 = wave_sum(part2);
+  if (lane == 0) {
+    s_wp[0][w] = part;
+    s_wp[1][w] = part2;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    if (MODE == MODE_TRANS) d->part_phi[t] = part;
-    else d->part_rho[t] = part;
-    if (MODE == MODE_REFINE) d->part_b[t] = part2;
+    double a = s_wp[0][0], b2 = s_wp[1][0];
+#pragma unroll
+    for (int q = 1; q < kWaves; ++q) {
+      a += s_wp[0][q];
+      b2 += s_wp[1][q];
+    }
+    const int t = ent.y;
+    if (MODE == MODE_TRANS) d->part_phi[t] = a;
+    else d->part_rho[t] = a;
+    if (MODE == MODE_REFINE) d->part_b[t] = b2;
   }
 }
 
@@ -250,13 +346,13 @@ __global__ __launch_bounds__(kWG) void k_axpy_out(const Desc* __restrict__ D,
 }
 
 // nu = ||b - A x||; finish, or start a new inner solve.
-__global__ __launch_bounds__(kWG) void k_outer(const Desc* __restrict__ D, const int* __restrict__ sys) {
-  __shared__ double s_red[kWaves];
+__global__ __launch_bounds__(kRW) void k_outer(const Desc* __restrict__ D, const int* __restrict__ sys) {
+  __shared__ double s_red[kRW / 64];
   const Desc* d = D + sys[blockIdx.x];
   State* st = d->st;
   if (st->final_done || !st->done) return;
-  const double rr = block_sum_array(d->part_rho, d->a_ntiles, s_red);
-  const double bb = block_sum_array(d->part_b, d->a_ntiles, s_red);
+  const double rr = big_sum_array(d->part_rho, d->a_ntiles, s_red);
+  const double bb = big_sum_array(d->part_b, d->a_ntiles, s_red);
   if (threadIdx.x != 0) return;
   const double nu = sqrt(rr);
   if (st->outer == 0) st->nb_out = sqrt(bb);
@@ -299,44 +395,52 @@ __global__ __launch_bounds__(kWG) void k_outer(const Desc* __restrict__ D, const
 // r <- c (inner right-hand side), partial rho and ||c||^2, on the CSR tiles.
 template <class Vec>
 __global__ __launch_bounds__(kWG) void k_start(const Desc* __restrict__ D, const int2* __restrict__ list) {
-  __shared__ double s_red[kWaves];
+  __shared__ double s_wp[kWaves];
   const int2 ent = list[blockIdx.x];
   const Desc* d = D + ent.x;
   const State* st = d->st;
   if (st->final_done || st->done || st->k != 0) return;
-  const int r0 = d->a_tile[ent.y], r1 = d->a_tile[ent.y + 1];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wt = d->a_grp[ent.y * kWaves + w];
   const double inv = d->is_f32 ? 1.0 / st->nu : 1.0;
   Vec* r = static_cast<Vec*>(d->r);
   Vec* c = static_cast<Vec*>(d->c);
   double part = 0.0;
-  for (int i = r0 + threadIdx.x; i < r1; i += kWG) {
-    const Vec ci = Vec(d->r64[i] * inv);
-    r[i] = ci;
-    if (c) c[i] = ci;
-    part += double(ci) * double(ci);
+  if (wt >= 0) {
+    const int r0 = d->a_tile[wt], r1 = d->a_tile[wt + 1];
+    for (int i = r0 + lane; i < r1; i += 64) {
+      const Vec ci = Vec(d->r64[i] * inv);
+      r[i] = ci;
+      if (c) c[i] = ci;
+      part += double(ci) * double(ci);
+    }
   }
-  part = block_sum(part, s_red);
+  part = wave_sum(part);
+  if (lane == 0) s_wp[w] = part;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    d->part_rho[ent.y] = part;
-    d->part_b[ent.y] = part;
+    double a = s_wp[0];
+    for (int q = 1; q < kWaves; ++q) a += s_wp[q];
+    d->part_rho[ent.y] = a;
+    d->part_b[ent.y] = a;
   }
 }
 
 // ------------------------------------------------------------------ inner step scalars
 
 // Algorithm 1: rho, stop test, phi, theta, beta, gamma (one workgroup per system).
-__global__ __launch_bounds__(kWG) void k_step(const Desc* __restrict__ D, const int* __restrict__ sys) {
-  __shared__ double s_red[kWaves];
+__global__ __launch_bounds__(kRW) void k_step(const Desc* __restrict__ D, const int* __restrict__ sys) {
+  __shared__ double s_red[kRW / 64];
   const Desc* d = D + sys[blockIdx.x];
   State* st = d->st;
   if (st->final_done || st->done) return;
-  const double rho = block_sum_array(d->part_rho, d->a_ntiles, s_red);
-  const double phi = block_sum_array(d->part_phi, d->t_ntiles, s_red);
+  const double rho = big_sum_array(d->part_rho, d->a_ntiles, s_red);
+  const double phi = big_sum_array(d->part_phi, d->t_ntiles, s_red);
   const long long k = st->k;
   double theta = 0.0;
-  if (k > 0) theta = block_sum_array(d->part_theta, d->u_nblk, s_red);
+  if (k > 0) theta = big_sum_array(d->part_theta, d->u_nblk, s_red);
   double nbi = 0.0;
-  if (k == 0) nbi = block_sum_array(d->part_b, d->a_ntiles, s_red);
+  if (k == 0) nbi = big_sum_array(d->part_b, d->a_ntiles, s_red);
   if (threadIdx.x != 0) return;
 
   if (k == 0) {
@@ -619,7 +723,7 @@ void launch_axpy_out(const Desc* d, const int2* ulist, int n, hipStream_t s) {
 }
 void launch_outer(const Desc* d, const int* sys, int n, hipStream_t s) {
   if (n <= 0) return;
-  k_outer<<<n, kWG, 0, s>>>(d, sys);
+  k_outer<<<n, kRW, 0, s>>>(d, sys);
 }
 void launch_start(bool f32, const Desc* d, const int2* alist, int n, hipStream_t s) {
   if (n <= 0) return;
@@ -628,7 +732,7 @@ void launch_start(bool f32, const Desc* d, const int2* alist, int n, hipStream_t
 }
 void launch_step(const Desc* d, const int* sys, int n, hipStream_t s) {
   if (n <= 0) return;
-  k_step<<<n, kWG, 0, s>>>(d, sys);
+  k_step<<<n, kRW, 0, s>>>(d, sys);
 }
 void launch_update(bool f32, const Desc* d, const int2* ulist, int n, hipStream_t s) {
   if (n <= 0) return;

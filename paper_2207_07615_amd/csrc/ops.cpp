@@ -30,11 +30,15 @@ void plain_launch(const plss_matrix* A, bool transpose, const double* dx, double
   d.a_val = A->A.val;
   d.a_tile = A->A.tile;
   d.a_ntiles = A->A.ntiles;
+  d.a_nwt = A->A.nwt;
+  d.a_grp = A->A.grp;
   d.t_ptr = A->T.ptr;
   d.t_idx = A->T.idx;
   d.t_val = A->T.val;
   d.t_tile = A->T.tile;
   d.t_ntiles = A->T.ntiles;
+  d.t_nwt = A->T.nwt;
+  d.t_grp = A->T.grp;
   d.m = (int)A->m;
   d.n = (int)A->n;
   d.p = const_cast<double*>(dx);

@@ -45,13 +45,45 @@ std::vector<int> make_tiles(const std::vector<int>& ptr, int V) {
   return t;
 }
 
+// Groups of 4 wave tiles for one workgroup each.  Tiles of one long row
+// are sorted by length (longest first) and grouped with tiles of similar
+// length, so no workgroup waits on one long row beside three short tiles;
+// short tiles are grouped in row order.  Long groups come first in the
+// launch order.
+std::vector<int> make_groups(const std::vector<int>& ptr, const std::vector<int>& tiles, int V) {
+  const int TW = tile_nnz(V);
+  const int nwt = (int)tiles.size() - 1;
+  std::vector<int> lng, sht;
+  for (int t = 0; t < nwt; ++t) {
+    const long long ne = (long long)ptr[tiles[t + 1]] - ptr[tiles[t]];
+    (ne > TW ? lng : sht).push_back(t);
+  }
+  std::stable_sort(lng.begin(), lng.end(), [&](int a, int b) {
+    return ptr[tiles[a] + 1] - ptr[tiles[a]] > ptr[tiles[b] + 1] - ptr[tiles[b]];
+  });
+  std::vector<int> g;
+  for (auto* v : {&lng, &sht}) {
+    for (size_t i = 0; i < v->size(); i += kWaves)
+      for (int w = 0; w < kWaves; ++w) g.push_back(i + w < v->size() ? (*v)[i + w] : -1);
+  }
+  if (g.empty()) g.assign(kWaves, -1);
+  return g;
+}
+
 void set_tiles(PlssDir& d, int V, hipStream_t s) {
   std::vector<int> t = make_tiles(d.h_ptr, V);
+  std::vector<int> g = make_groups(d.h_ptr, t, V);
   dfree(d.tile);
+  dfree(d.grp);
+  d.tile = nullptr;
+  d.grp = nullptr;
   d.tile = static_cast<int*>(dmalloc(sizeof(int) * t.size()));
+  d.grp = static_cast<int*>(dmalloc(sizeof(int) * g.size()));
   PLSS_HIP(hipMemcpyAsync(d.tile, t.data(), sizeof(int) * t.size(), hipMemcpyHostToDevice, s));
+  PLSS_HIP(hipMemcpyAsync(d.grp, g.data(), sizeof(int) * g.size(), hipMemcpyHostToDevice, s));
   PLSS_HIP(hipStreamSynchronize(s));
-  d.ntiles = (int)t.size() - 1;
+  d.nwt = (int)t.size() - 1;
+  d.ntiles = (int)g.size() / kWaves;
   d.V = V;
 }
 
@@ -161,6 +193,7 @@ void matrix_destroy(plss_matrix* M) {
     dfree(d->idx);
     dfree(d->val);
     dfree(d->tile);
+    dfree(d->grp);
   }
   delete M;
 }

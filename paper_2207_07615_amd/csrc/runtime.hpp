@@ -14,9 +14,11 @@ struct PlssDir {
   int* ptr = nullptr;    // nrows + 1
   int* idx = nullptr;    // nnz
   void* val = nullptr;   // nnz, f64 or f32
-  int* tile = nullptr;   // ntiles + 1
-  int ntiles = 0;
-  int V = 8;             // entries per thread of a tile (tile = 256*V entries)
+  int* tile = nullptr;   // nwt + 1 row starts of the wave tiles
+  int* grp = nullptr;    // 4 * ntiles wave-tile ids (-1 = none)
+  int nwt = 0;           // wave tiles
+  int ntiles = 0;        // groups of 4 wave tiles (workgroups per launch)
+  int V = 8;             // entries per lane of a wave tile (64*V entries)
   std::vector<int> h_ptr;  // host copy of ptr (tile construction)
 };
 
@@ -48,6 +50,7 @@ void dfree(void* p);
 
 // tile table of a pointer array for tiles of 256*V entries
 std::vector<int> make_tiles(const std::vector<int>& ptr, int V);
+std::vector<int> make_groups(const std::vector<int>& ptr, const std::vector<int>& tiles, int V);
 void set_tiles(PlssDir& d, int V, hipStream_t s);
 
 // validated store creation (throws InvalidArg / OutOfMemory / DeviceError)

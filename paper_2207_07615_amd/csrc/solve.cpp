@@ -60,11 +60,15 @@ void SysRun::setup(const plss_matrix* M, const double* b_in, const plss_opts* o,
   desc.a_val = M->A.val;
   desc.a_tile = M->A.tile;
   desc.a_ntiles = M->A.ntiles;
+  desc.a_nwt = M->A.nwt;
+  desc.a_grp = M->A.grp;
   desc.t_ptr = M->T.ptr;
   desc.t_idx = M->T.idx;
   desc.t_val = M->T.val;
   desc.t_tile = M->T.tile;
   desc.t_ntiles = M->T.ntiles;
+  desc.t_nwt = M->T.nwt;
+  desc.t_grp = M->T.grp;
   desc.m = (int)m;
   desc.n = (int)n;
   desc.u_nblk = u_nblk;
