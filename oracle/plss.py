@@ -175,13 +175,15 @@ def column_sequence(kind: str, m: int, perm=None) -> Iterable[tuple]:
 
 def plss_columns(A, b, sketch="identity", perm=None, tol=1e-8, maxit=1000,
                  tol_absolute=False, hist_cap=None, max_columns=None,
-                 record=False) -> Result:
+                 record=False, dot=None) -> Result:
     """PLSS with a sketch grown by one column per step (identity, mixed or
     residual columns), storing P = [p_1..p_k], AP = [A p_1..A p_k] and
     Θ = diag(p_jᵀ p_j) as in Section 7.  W = I.
 
     ``maxit`` bounds applied updates; ``max_columns`` (default 4*maxit + 4*m)
-    bounds columns examined, including skipped ones."""
+    bounds columns examined, including skipped ones.  ``dot`` replaces the
+    inner product (default ``numpy.dot``), as in ``plss_residual``."""
+    dot = dot or (lambda a, c: float(a @ c))
     S = _as_sparse(A)
     m, n = S.shape
     b = np.asarray(b, dtype=np.float64)
@@ -194,7 +196,7 @@ def plss_columns(A, b, sketch="identity", perm=None, tol=1e-8, maxit=1000,
 
     x = np.zeros(n)
     r = b.copy()
-    rho = float(r @ r)
+    rho = dot(r, r)
     hist = [math.sqrt(rho) * scale]
     P: List[np.ndarray] = []
     AP: List[np.ndarray] = []
@@ -217,7 +219,7 @@ def plss_columns(A, b, sketch="identity", perm=None, tol=1e-8, maxit=1000,
         th = np.array(Theta)
         if col[0] == "r":
             y = S.T @ r                                   # y = Aᵀ r
-            w = np.array([ap @ r for ap in AP])          # (AP)ᵀ r = Pᵀ y
+            w = np.array([dot(ap, r) for ap in AP])      # (AP)ᵀ r = Pᵀ y
             sigma = rho                                   # r_{k-1}ᵀ r_{k-1}
         else:
             i = col[1]
@@ -228,7 +230,7 @@ def plss_columns(A, b, sketch="identity", perm=None, tol=1e-8, maxit=1000,
             sigma = float(r[i])                          # e_iᵀ r_{k-1}
         c = w / th if len(Theta) else np.zeros(0)
         q = y - (np.column_stack(P) @ c if P else 0.0)
-        yy = float(y @ y)
+        yy = dot(y, y)
         na = math.sqrt(yy)
         nd = math.sqrt(float(np.sum(w * w / th))) if len(Theta) else 0.0
         delta = (na - nd) * (na + nd)
@@ -243,9 +245,9 @@ def plss_columns(A, b, sketch="identity", perm=None, tol=1e-8, maxit=1000,
         Ap = S @ p
         r = r - Ap
         x = x + p
-        P.append(p); AP.append(Ap); Theta.append(float(p @ p))
+        P.append(p); AP.append(Ap); Theta.append(dot(p, p))
         k += 1
-        rho = float(r @ r)
+        rho = dot(r, r)
         hist.append(math.sqrt(rho) * scale)
         if record:
             xs.append(x.copy()); ps.append(p.copy()); rs.append(r.copy()); used.append(col[:2])

@@ -195,12 +195,15 @@ def _info_dict(inf: L.plss_info):
             "status_name": status_name(inf.status), "ms": inf.ms}
 
 
-def solve(handle: Handle, A: Matrix, b, hist_cap: int = 0, **kw):
-    """Solve A x = b.  Returns (x, info dict, residual history array)."""
+def solve(handle: Handle, A: Matrix, b, hist_len: int = 0, **kw):
+    """Solve A x = b.  Returns (x, info dict, residual history array of at
+    most hist_len entries; default maxit + 2).  Keyword options are those of
+    plss_opts (sketch, tol, maxit, refine, inner_tol, x0, wi, row_perm,
+    hist_cap = identity/mixed history capacity, ...)."""
     bb = _Arr(b, np.float64)
     o, keep = make_opts(**kw)
     x, xp = _out_like(bb, (A.n,))
-    hc = int(hist_cap) if hist_cap else int(min(kw.get("maxit", 1000) + 2, 1 << 20))
+    hc = int(hist_len) if hist_len else int(min(kw.get("maxit", 1000) + 2, 1 << 20))
     hist = np.empty(hc, np.float64)
     inf = L.plss_info()
     _check(_clib().plss_solve(handle.h, A.A, bb.ptr, C.byref(o), xp, hist.ctypes.data, hc, C.byref(inf)))

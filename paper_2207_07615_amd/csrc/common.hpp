@@ -61,6 +61,7 @@ struct State {
   long long kh;                // stored history columns
   long long col;               // sketch columns examined
   long long hist_cap;          // history capacity
+  long long max_cols;          // bound on sketch columns examined (skips included)
   int skip;                    // current column skipped
   int col_kind;                // 0 residual column, 1 identity column
   int row;                     // identity row of the current column

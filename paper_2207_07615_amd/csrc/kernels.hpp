@@ -23,9 +23,10 @@ void convert_vals(const double* src, long long nnz, bool f32, void* dst, hipStre
 void ptr64_to_32(const long long* src, int n1, int* dst, hipStream_t s);
 
 // one-column sketch steps (identity / mixed)
-void launch_sketch_step(const Desc* d, int ndesc_unused, int V, const int2* alist, int na,
-                        const int2* tlist, int nt, const int2* ulist, int nu, const int2* wlist,
-                        int nw, const int* sys, int ns, bool residual_column, hipStream_t s);
+void launch_col_init(const Desc* d, const int* sys, int ns, hipStream_t s);
+void launch_sketch_step(const Desc* d, int V, const int2* alist, int na, const int2* tlist, int nt,
+                        const int2* ulist, int nu, const int2* wlist, int nw, const int* sys, int ns,
+                        bool residual_column, int VT, hipStream_t s);
 
 }  // namespace plss
 

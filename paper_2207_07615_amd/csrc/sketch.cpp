@@ -1,0 +1,157 @@
+// Driver of the identity and mixed sketches (one sketch column per step).
+#include "sketch.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "solve.hpp"
+
+namespace plss {
+
+namespace {
+size_t up(size_t v) { return (v + 255) / 256 * 256; }
+}  // namespace
+
+void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const plss_opts* o, double* x,
+                  double* hist, long long hist_cap_out, plss_info* info, hipStream_t s) {
+  if (A->f32) throw InvalidArg{"identity/mixed sketches need float64 storage"};
+  if (o->wi_diag) throw InvalidArg{"wi_diag applies to the residual sketch only"};
+  if (o->x0) throw InvalidArg{"identity/mixed sketches start from x0 = 0"};
+  check_finite_inputs(A, b, o, s);
+  const int m = (int)A->m, n = (int)A->n;
+  long long cap = o->hist_cap > 0 ? o->hist_cap : std::min<long long>({(long long)m, (long long)n, 256});
+  if (cap > 256) throw InvalidArg{"hist_cap must be at most 256"};
+  cap = std::min<long long>(cap, std::min(m, n));
+  // row order: validated permutation of 0..m-1
+  std::vector<int> perm(m);
+  if (o->row_perm) {
+    PLSS_HIP(hipMemcpy(perm.data(), o->row_perm, sizeof(int) * m, hipMemcpyDefault));
+    std::vector<char> seen(m, 0);
+    for (int i = 0; i < m; ++i) {
+      if (perm[i] < 0 || perm[i] >= m || seen[perm[i]]) throw InvalidArg{"row_perm is not a permutation"};
+      seen[perm[i]] = 1;
+    }
+  } else {
+    for (int i = 0; i < m; ++i) perm[i] = i;
+  }
+
+  State* d_state = static_cast<State*>(dmalloc(sizeof(State)));
+  Desc* d_desc = static_cast<Desc*>(dmalloc(sizeof(Desc)));
+  SysRun run;
+  char* extra = nullptr;
+  char* d_lists = nullptr;
+  State* h_state = nullptr;
+  try {
+    run.setup(A, b, o, std::min<long long>(o->maxit + 2, 1LL << 22), d_state, nullptr);
+    run.upload(b, nullptr, nullptr, s);
+    const int wblk = (m + 1023) / 1024;
+    // history and scratch: P (n x cap), AP (m x cap), Θ, c, partial w, dense row, order
+    size_t off = 0;
+    const size_t oP = off; off = up(off + 8 * (size_t)n * cap);
+    const size_t oAP = off; off = up(off + 8 * (size_t)m * cap);
+    const size_t oTh = off; off = up(off + 8 * (size_t)cap);
+    const size_t oCv = off; off = up(off + 8 * (size_t)cap);
+    const size_t oPw = off; off = up(off + 8 * (size_t)cap * wblk);
+    const size_t oDn = off; off = up(off + 8 * (size_t)n);
+    const size_t oPm = off; off = up(off + 4 * (size_t)m);
+    extra = static_cast<char*>(dmalloc(off));
+    PLSS_HIP(hipMemsetAsync(extra + oDn, 0, 8 * (size_t)n, s));
+    PLSS_HIP(hipMemcpyAsync(extra + oPm, perm.data(), 4 * (size_t)m, hipMemcpyHostToDevice, s));
+    Desc d = run.desc;
+    d.P = reinterpret_cast<double*>(extra + oP);
+    d.AP = reinterpret_cast<double*>(extra + oAP);
+    d.Th = reinterpret_cast<double*>(extra + oTh);
+    d.cv = reinterpret_cast<double*>(extra + oCv);
+    d.part_w = reinterpret_cast<double*>(extra + oPw);
+    d.wblk = wblk;
+    d.dense = reinterpret_cast<double*>(extra + oDn);
+    d.perm = reinterpret_cast<const int*>(extra + oPm);
+    d.sketch = o->sketch == PLSS_SKETCH_IDENTITY ? 1 : 2;
+    State st = run.st0;
+    st.hist_cap = cap;
+    st.max_cols = 4 * o->maxit + 4 * (long long)m;
+    PLSS_HIP(hipMemcpyAsync(d_desc, &d, sizeof(Desc), hipMemcpyHostToDevice, s));
+    PLSS_HIP(hipMemcpyAsync(d_state, &st, sizeof(State), hipMemcpyHostToDevice, s));
+
+    // lists: CSR groups, CSC groups, update blocks, (AP)ᵀ r blocks, the system
+    std::vector<int2> la, lt, lu, lw;
+    for (int t = 0; t < A->A.ntiles; ++t) la.push_back(make_int2(0, t));
+    for (int t = 0; t < A->T.ntiles; ++t) lt.push_back(make_int2(0, t));
+    for (int t = 0; t < run.u_nblk; ++t) lu.push_back(make_int2(0, t));
+    for (int t = 0; t < wblk; ++t) lw.push_back(make_int2(0, t));
+    const size_t nl = la.size() + lt.size() + lu.size() + lw.size();
+    d_lists = static_cast<char*>(dmalloc(sizeof(int2) * nl + 64));
+    int2* dla = reinterpret_cast<int2*>(d_lists);
+    int2* dlt = dla + la.size();
+    int2* dlu = dlt + lt.size();
+    int2* dlw = dlu + lu.size();
+    int* dsys = reinterpret_cast<int*>(dlw + lw.size());
+    std::vector<int2> all;
+    all.insert(all.end(), la.begin(), la.end());
+    all.insert(all.end(), lt.begin(), lt.end());
+    all.insert(all.end(), lu.begin(), lu.end());
+    all.insert(all.end(), lw.begin(), lw.end());
+    PLSS_HIP(hipMemcpyAsync(d_lists, all.data(), sizeof(int2) * nl, hipMemcpyHostToDevice, s));
+    PLSS_HIP(hipMemsetAsync(dsys, 0, sizeof(int), s));
+    PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_state), sizeof(State), hipHostMallocDefault));
+
+    auto outer_seq = [&]() {
+      launch_spmv(MODE_REFINE, false, A->A.V, d_desc, dla, (int)la.size(), 0, s);
+      launch_outer(d_desc, dsys, 1, s);
+      launch_start(false, d_desc, dla, (int)la.size(), s);
+    };
+    hipEvent_t e0, e1;
+    PLSS_HIP(hipEventCreate(&e0));
+    PLSS_HIP(hipEventCreate(&e1));
+    PLSS_HIP(hipEventRecord(e0, s));
+    outer_seq();
+    launch_col_init(d_desc, dsys, 1, s);
+    long long t = 0;
+    int chunk = o->chunk > 0 ? o->chunk : 16;
+    while (true) {
+      for (int c = 0; c < chunk; ++c, ++t) {
+        const bool resid = (d.sketch == 2) && (t % 2 == 0);
+        launch_sketch_step(d_desc, A->A.V, dla, (int)la.size(), dlt, (int)lt.size(), dlu, (int)lu.size(),
+                           dlw, (int)lw.size(), dsys, 1, resid, A->T.V, s);
+      }
+      PLSS_HIP(hipMemcpyAsync(h_state, d_state, sizeof(State), hipMemcpyDeviceToHost, s));
+      PLSS_HIP(hipStreamSynchronize(s));
+      if (h_state->done || h_state->final_done) break;
+      if (o->chunk <= 0) chunk = std::min(chunk * 2, 128);
+    }
+    outer_seq();  // true residual of the final x
+    PLSS_HIP(hipMemcpyAsync(h_state, d_state, sizeof(State), hipMemcpyDeviceToHost, s));
+    PLSS_HIP(hipEventRecord(e1, s));
+    PLSS_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    PLSS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    const State& fs = *h_state;
+    PLSS_HIP(hipMemcpyAsync(x, run.desc.xo, 8 * (size_t)n, hipMemcpyDefault, s));
+    const long long nh = std::min<long long>({hist_cap_out, fs.k_total + 1, run.hist_len});
+    if (hist && nh > 0) PLSS_HIP(hipMemcpyAsync(hist, run.desc.hist, 8 * nh, hipMemcpyDefault, s));
+    PLSS_HIP(hipStreamSynchronize(s));
+    info->iters = fs.k_total;
+    info->outer_iters = fs.col;  // sketch columns examined
+    info->relres = sqrt(fs.rho) * fs.scale;
+    info->relres_true = fs.relres_true;
+    info->status = fs.final_done ? fs.final_status : fs.status;
+    info->ms = ms;
+  } catch (...) {
+    dfree(extra);
+    dfree(d_lists);
+    dfree(d_state);
+    dfree(d_desc);
+    if (h_state) (void)hipHostFree(h_state);
+    throw;
+  }
+  dfree(extra);
+  dfree(d_lists);
+  dfree(d_state);
+  dfree(d_desc);
+  (void)hipHostFree(h_state);
+}
+
+}  // namespace plss

@@ -3,10 +3,6 @@
 #include "serve.hpp"
 #include "sketch.hpp"
 namespace plss {
-void sketch_solve(plss_handle*, const plss_matrix*, const double*, const plss_opts*, double*, double*,
-                  long long, plss_info*, hipStream_t) {
-  throw InvalidArg{"identity/mixed sketch not built yet"};
-}
 plss_status multi_solve(plss_handle*, const plss_matrix*, int, const double*, const plss_opts*, double*,
                         plss_info*, hipStream_t) {
   throw InvalidArg{"multi-RHS not built yet"};

@@ -1,0 +1,129 @@
+"""GPU parity of the identity (Section 7) and mixed sketches against the
+oracle's one-column step, at equal update counts (see gpu_common)."""
+import sys
+
+import numpy as np
+import pytest
+
+import plss_inputs as gen
+from oracle import pins
+from oracle import plss as O
+
+from gpu_common import chunk_dot, fsum_dot, matrix, rel, rev_dot
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def h():
+    import paper_2207_07615_amd as plss
+    return plss.Handle(0)
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def column_parity(h, sysm, sketch, tol, maxit, cap):
+    import paper_2207_07615_amd as plss
+    M = matrix(h, sysm.A)
+    x, info, hist = plss.solve(h, M, sysm.b, sketch=sketch, tol=tol, maxit=maxit,
+                               row_perm=sysm.perm, hist_cap=cap)
+    k = info["iters"]
+    ref = O.plss_columns(sysm.A, sysm.b, sketch, perm=sysm.perm, tol=1e-300, maxit=k, hist_cap=cap)
+    spread = 0.0
+    for dot in (fsum_dot, rev_dot, chunk_dot):
+        alt = O.plss_columns(sysm.A, sysm.b, sketch, perm=sysm.perm, tol=1e-300, maxit=k,
+                             hist_cap=cap, dot=dot)
+        spread = max(spread, rel(alt.x, ref.x))
+    err = rel(x, ref.x)
+    say(f"  {sketch}: updates={k} columns={info['outer_iters']} err={err:.3e} spread={spread:.3e}")
+    assert ref.iters == k
+    assert err <= max(1e-10, 4 * spread)
+    return x, info, hist, ref
+
+
+@pytest.mark.parametrize("sketch", ["identity", "mixed"])
+def test_tiny_sketch_matches_oracle(h, sketch):
+    say("tiny", sketch)
+    sysm = gen.tiny(31, 60, 150, 8, "uniform")
+    x, info, hist, ref = column_parity(h, sysm, sketch, 1e-10, 4000, 60)
+    assert info["status"] == 0
+    np.testing.assert_allclose(hist[:5], ref.hist[:5], rtol=1e-9)
+
+
+def test_identity_underdetermined_reaches_min_norm(h):
+    """Corollary 2: a full pass of identity columns on a full-row-rank
+    64 x 256 system gives A†b."""
+    import paper_2207_07615_amd as plss
+    say("cor2")
+    sysm = gen.tiny(77, 64, 256, 30, "uniform")
+    M = matrix(h, sysm.A)
+    x, info, _ = plss.solve(h, M, sysm.b, sketch="identity", tol=1e-12, maxit=64,
+                            row_perm=sysm.perm, hist_cap=64)
+    xm = pins.min_norm(sysm.A.dense(), sysm.b)
+    assert info["iters"] <= 64
+    assert rel(x, xm) <= 1e-10
+
+
+def test_identity_orthogonal_rows_is_kaczmarz(h):
+    """Rows with disjoint supports: each step is the Kaczmarz step."""
+    import paper_2207_07615_amd as plss
+    from gpu_common import csr_from_dense
+    say("kaczmarz")
+    m, n = 6, 18
+    rng = np.random.default_rng(5)
+    D = np.zeros((m, n))
+    cols = rng.permutation(n)
+    for i in range(m):
+        D[i, cols[3 * i:3 * i + 3]] = rng.standard_normal(3)
+    b = D @ rng.standard_normal(n)
+    order = rng.permutation(m).astype(np.int32)
+    rp, ci, va = csr_from_dense(D)
+    M = plss.Matrix(h, rp, ci, va, shape=(m, n))
+    kz = pins.kaczmarz(D, b, order)
+    for k in range(1, m + 1):
+        x, info, _ = plss.solve(h, M, b, sketch="identity", tol=1e-300, maxit=k, row_perm=order)
+        assert rel(x, kz[k - 1]) <= 1e-13
+
+
+@pytest.mark.parametrize("cap", [3, 7])
+def test_history_cap_matches_oracle(h, cap):
+    """A small history capacity clears P, AP, Θ periodically on both sides."""
+    say("cap", cap)
+    sysm = gen.tiny(41, 80, 200, 10, "uniform")
+    column_parity(h, sysm, "mixed", 1e-9, 3000, cap)
+
+
+def test_mixed_underdetermined_medium(h):
+    """The underdetermined recipe (30 nnz per row, U(-1,1)) at 20,000 x
+    100,000, mixed sketch, tol 1e-8, against the oracle and A†b-consistency."""
+    say("mixed medium")
+    sysm = gen.underdet(m=20000, n=100000)
+    x, info, hist, ref = column_parity(h, sysm, "mixed", 1e-8, 2000, 64)
+    assert info["status"] == 0
+    assert info["relres_true"] <= 1.5e-8
+    # x lies in range(Aᵀ) (x0 = 0), so it is the minimum-norm solution up to
+    # the residual: compare with the oracle's converged iterate
+    full = O.plss_columns(sysm.A, sysm.b, "mixed", perm=sysm.perm, tol=1e-8, maxit=2000, hist_cap=64)
+    assert abs(full.iters - info["iters"]) <= 1
+
+
+def test_sketch_edge_cases(h):
+    import paper_2207_07615_amd as plss
+    say("sketch edges")
+    sysm = gen.tiny(55, 40, 90, 6)
+    M = matrix(h, sysm.A)
+    x, info, _ = plss.solve(h, M, np.zeros(40), sketch="mixed", tol=1e-8, maxit=10, row_perm=sysm.perm)
+    assert info["iters"] == 0 and not np.any(x)
+    x, info, _ = plss.solve(h, M, sysm.b, sketch="identity", tol=1e-14, maxit=1, row_perm=sysm.perm)
+    ref = O.plss_columns(sysm.A, sysm.b, "identity", perm=sysm.perm, tol=1e-14, maxit=1)
+    assert info["iters"] == 1 and rel(x, ref.x) <= 1e-13
+    bad = np.arange(40, dtype=np.int32)
+    bad[3] = 4
+    with pytest.raises(plss.PlssError):
+        plss.solve(h, M, sysm.b, sketch="identity", tol=1e-8, maxit=10, row_perm=bad)
+    M32 = matrix(h, sysm.A, "f32")
+    with pytest.raises(plss.PlssError):
+        plss.solve(h, M32, sysm.b, sketch="identity", tol=1e-8, maxit=10)
