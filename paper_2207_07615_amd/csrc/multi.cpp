@@ -1,0 +1,199 @@
+// Driver of the many-right-hand-side path: columns advance in lock-step;
+// each column has its own stop test, and the refinement (float32 storage)
+// outer step runs when every unfinished column has finished its inner solve.
+#include "multi.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <vector>
+
+#include "multi_kernels.hpp"
+#include "solve.hpp"
+
+namespace plss {
+
+namespace {
+size_t up(size_t v) { return (v + 255) / 256 * 256; }
+
+plss_status run_group(plss_handle* h, const plss_matrix* A, int ncols, const double* Bcm, const plss_opts* o,
+                      double* Xcm, plss_info* info, hipStream_t s) {
+  const bool f32 = A->f32;
+  const int m = (int)A->m, n = (int)A->n;
+  int W = 8;
+  while (W < ncols) W *= 2;
+  const size_t vs = f32 ? 4 : 8;
+  const int na_blk = (m + kRB - 1) / kRB, nt_blk = (n + kRB - 1) / kRB;
+  const int nu_blk = (int)(((long long)n * W + 4095) / 4096);
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t r = off;
+    off = up(off + b);
+    return r;
+  };
+  const size_t oB = take(8ull * m * W), oR64 = take(8ull * m * W), oR = take(vs * m * W);
+  const size_t oP = take(vs * n * W), oY = take(vs * n * W), oX = take(8ull * n * W);
+  const size_t oXi = f32 ? take(8ull * n * W) : 0;
+  const size_t oPr = take(8ull * na_blk * W), oPb = take(8ull * na_blk * W);
+  const size_t oPp = take(8ull * nt_blk * W), oPt = take(8ull * nu_blk * W);
+  const size_t oBin = take(8ull * m * ncols);
+  const size_t oSt = take(sizeof(MState)), oD = take(sizeof(MDesc));
+  char* ar = static_cast<char*>(dmalloc(off));
+  MState* hst = nullptr;
+  plss_status agg = PLSS_OK;
+  try {
+    MDesc d{};
+    d.a_ptr = A->A.ptr;
+    d.a_idx = A->A.idx;
+    d.a_val = A->A.val;
+    d.t_ptr = A->T.ptr;
+    d.t_idx = A->T.idx;
+    d.t_val = A->T.val;
+    d.m = m;
+    d.n = n;
+    d.s = W;
+    d.W = W;
+    d.na_blk = na_blk;
+    d.nt_blk = nt_blk;
+    d.nu_blk = nu_blk;
+    d.is_f32 = f32;
+    d.R = ar + oR;
+    d.P = ar + oP;
+    d.Y = ar + oY;
+    d.X = reinterpret_cast<double*>(ar + oX);
+    d.Xi = f32 ? reinterpret_cast<double*>(ar + oXi) : d.X;
+    d.B = reinterpret_cast<double*>(ar + oB);
+    d.R64 = reinterpret_cast<double*>(ar + oR64);
+    d.part_rho = reinterpret_cast<double*>(ar + oPr);
+    d.part_b = reinterpret_cast<double*>(ar + oPb);
+    d.part_phi = reinterpret_cast<double*>(ar + oPp);
+    d.part_theta = reinterpret_cast<double*>(ar + oPt);
+    d.st = reinterpret_cast<MState*>(ar + oSt);
+    MDesc* dd = reinterpret_cast<MDesc*>(ar + oD);
+    // right-hand sides: caller's column-major block -> row-major, padded
+    PLSS_HIP(hipMemcpyAsync(ar + oBin, Bcm, 8ull * m * ncols, hipMemcpyDefault, s));
+    launch_transpose_in(reinterpret_cast<double*>(ar + oBin), m, ncols, W, const_cast<double*>(d.B), s);
+    PLSS_HIP(hipMemsetAsync(d.X, 0, 8ull * n * W, s));
+    if (f32) PLSS_HIP(hipMemsetAsync(d.Xi, 0, 8ull * n * W, s));
+    PLSS_HIP(hipMemsetAsync(d.P, 0, vs * n * W, s));
+    MState st;
+    std::memset(&st, 0, sizeof(st));
+    for (int c = 0; c < kMaxCols; ++c) {
+      st.done[c] = 1;
+      st.final_[c] = c >= ncols ? 1 : 0;
+      st.nu[c] = f32 ? 0.0 : 1.0;
+    }
+    st.tol = o->tol;
+    st.inner_tol = f32 && o->refine ? o->inner_tol : o->tol;
+    st.maxit = o->maxit;
+    st.max_outer = f32 && o->refine ? o->max_outer : 1;
+    st.tol_abs = o->tol_absolute ? 1 : 0;
+    PLSS_HIP(hipMemcpyAsync(d.st, &st, sizeof(st), hipMemcpyHostToDevice, s));
+    PLSS_HIP(hipMemcpyAsync(dd, &d, sizeof(d), hipMemcpyHostToDevice, s));
+    PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&hst), sizeof(MState), hipHostMallocDefault));
+
+    auto outer_step = [&]() {
+      launch_maxpy(dd, std::min(65536, (int)(((long long)n * W + 1023) / 1024)), s);
+      launch_spmm(MMODE_REFINE, f32, W, dd, na_blk, s);
+      launch_mouter(dd, s);
+      launch_mstart(f32, dd, na_blk, s);
+    };
+    hipEvent_t e0, e1;
+    PLSS_HIP(hipEventCreate(&e0));
+    PLSS_HIP(hipEventCreate(&e1));
+    PLSS_HIP(hipEventRecord(e0, s));
+    outer_step();
+    int chunk = o->chunk > 0 ? o->chunk : 8;
+    const bool timing = o->timing != 0;
+    std::vector<hipEvent_t> ev;
+    if (timing) {
+      ev.resize(5);
+      for (auto& e : ev) PLSS_HIP(hipEventCreate(&e));
+    }
+    while (true) {
+      for (int c = 0; c < chunk; ++c) {
+        if (timing) PLSS_HIP(hipEventRecord(ev[0], s));
+        launch_spmm(MMODE_RESID, f32, W, dd, na_blk, s);
+        if (timing) PLSS_HIP(hipEventRecord(ev[1], s));
+        launch_spmm(MMODE_TRANS, f32, W, dd, nt_blk, s);
+        if (timing) PLSS_HIP(hipEventRecord(ev[2], s));
+        launch_mstep(dd, s);
+        if (timing) PLSS_HIP(hipEventRecord(ev[3], s));
+        launch_mupdate(f32, dd, nu_blk, s);
+        if (timing) {
+          PLSS_HIP(hipEventRecord(ev[4], s));
+          PLSS_HIP(hipEventSynchronize(ev[4]));
+          for (int q = 0; q < 4; ++q) {
+            float ms = 0;
+            PLSS_HIP(hipEventElapsedTime(&ms, ev[q], ev[q + 1]));
+            h->kt_ms[q] += ms;
+            h->kt_n[q] += 1;
+          }
+        }
+      }
+      PLSS_HIP(hipMemcpyAsync(hst, d.st, sizeof(MState), hipMemcpyDeviceToHost, s));
+      PLSS_HIP(hipStreamSynchronize(s));
+      if (hst->all_done) break;
+      bool all_inner = true;
+      for (int c = 0; c < ncols; ++c) all_inner &= (hst->done[c] != 0);
+      if (all_inner) {
+        outer_step();
+        PLSS_HIP(hipMemcpyAsync(hst, d.st, sizeof(MState), hipMemcpyDeviceToHost, s));
+        PLSS_HIP(hipStreamSynchronize(s));
+        if (hst->all_done) break;
+      }
+      if (o->chunk <= 0) chunk = std::min(chunk * 2, 64);
+    }
+    PLSS_HIP(hipEventRecord(e1, s));
+    PLSS_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    PLSS_HIP(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (auto e : ev) (void)hipEventDestroy(e);
+    // solution: row-major padded -> caller's column-major block
+    double* tmp = reinterpret_cast<double*>(ar + oBin);  // reuse (n x ncols fits if n <= m)
+    double* out = tmp;
+    char* extra = nullptr;
+    if ((size_t)n * ncols > (size_t)m * ncols) {
+      extra = static_cast<char*>(dmalloc(8ull * n * ncols));
+      out = reinterpret_cast<double*>(extra);
+    }
+    launch_transpose_out(d.X, n, ncols, W, out, s);
+    PLSS_HIP(hipMemcpyAsync(Xcm, out, 8ull * n * ncols, hipMemcpyDefault, s));
+    PLSS_HIP(hipStreamSynchronize(s));
+    dfree(extra);
+    for (int c = 0; c < ncols; ++c) {
+      plss_info& inf = info[c];
+      inf.iters = hst->k_total[c];
+      inf.outer_iters = hst->outer - 1;
+      inf.relres = hst->nu[c] > 0 ? sqrt(hst->rho[c]) * hst->nu[c] / (hst->nb_out[c] > 0 ? hst->nb_out[c] : 1.0) : 0.0;
+      inf.relres_true = hst->relres_true[c];
+      inf.status = hst->final_status[c];
+      inf.ms = ms;
+      if (agg == PLSS_OK && inf.status != PLSS_OK) agg = (plss_status)inf.status;
+    }
+  } catch (...) {
+    dfree(ar);
+    if (hst) (void)hipHostFree(hst);
+    throw;
+  }
+  dfree(ar);
+  (void)hipHostFree(hst);
+  return agg;
+}
+}  // namespace
+
+plss_status multi_solve(plss_handle* h, const plss_matrix* A, int nrhs, const double* B, const plss_opts* o,
+                        double* X, plss_info* info, hipStream_t s) {
+  if (o->wi_diag || o->x0) throw InvalidArg{"multi-RHS solves take W = I and x0 = 0"};
+  if (!info) throw InvalidArg{"info array required"};
+  plss_status agg = PLSS_OK;
+  for (int c0 = 0; c0 < nrhs; c0 += kMaxCols) {
+    const int nc = std::min(kMaxCols, nrhs - c0);
+    const plss_status st = run_group(h, A, nc, B + (size_t)c0 * A->m, o, X + (size_t)c0 * A->n, info + c0, s);
+    if (agg == PLSS_OK) agg = st;
+  }
+  return agg;
+}
+
+}  // namespace plss

@@ -3,10 +3,6 @@
 #include "serve.hpp"
 #include "sketch.hpp"
 namespace plss {
-plss_status multi_solve(plss_handle*, const plss_matrix*, int, const double*, const plss_opts*, double*,
-                        plss_info*, hipStream_t) {
-  throw InvalidArg{"multi-RHS not built yet"};
-}
 plss_server* server_create(plss_handle*, size_t, int) { throw InvalidArg{"server not built yet"}; }
 plss_status server_submit(plss_server*, const plss_csr*, plss_dtype, const double*, const plss_opts*,
                           uint64_t*) {
