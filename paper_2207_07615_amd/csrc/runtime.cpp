@@ -200,8 +200,8 @@ void matrix_destroy(plss_matrix* M) {
 
 void handle_release(plss_handle* h) {
   if (!h) return;
-  h->refs -= 1;
-  if (h->closed && h->refs <= 0) {
+  const int left = --h->refs;
+  if (h->closed && left <= 0) {
     (void)hipStreamSynchronize(h->stream);
     (void)hipStreamDestroy(h->stream);
     delete h;

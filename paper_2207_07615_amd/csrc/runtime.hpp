@@ -1,6 +1,7 @@
 // Library-internal objects behind the opaque handles of plss.h.
 #pragma once
 
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -28,7 +29,7 @@ struct plss_handle {
   std::mutex mu;
   // matrices and servers created on the handle keep it alive: plss_destroy
   // only frees it once the last of them is destroyed
-  int refs = 0;
+  std::atomic<int> refs{0};
   bool closed = false;
   double kt_ms[4] = {0, 0, 0, 0};
   long long kt_n[4] = {0, 0, 0, 0};
