@@ -34,7 +34,10 @@ enum SpmvMode : int {
   MODE_REFINE = 2,  // out <- b - A x (float64) ; partial sum out^2, sum b^2
   MODE_PLAIN = 3,   // out <- A x (float64 in/out)
   MODE_AP = 4,      // ap <- A p ; r <- r - ap ; partial rho          (Section 7 storage of A p)
+  MODE_TRANSB = 5,  // ypart[b] <- A_bᵀ r_b for row block b (XCD-local gather of r)
 };
+
+constexpr int kMaxBlk = 8;         // row blocks of the transposed store (one per XCD)
 
 struct State {
   // Algorithm 1 scalars (float64 always)
@@ -88,6 +91,15 @@ struct Desc {
   int t_ntiles;
   int m, n;
   int u_nblk;                  // blocks of the vector-update kernel
+  // row-blocked CSC: block b holds the entries of rows [rb[b], rb[b+1])
+  int nblk;                    // 1: products with Aᵀ use the CSC above
+  const int* tb_ptr[kMaxBlk];
+  const int* tb_idx[kMaxBlk];
+  const void* tb_val[kMaxBlk];
+  const int* tb_tile[kMaxBlk];
+  const int* tb_grp[kMaxBlk];
+  void* ypart;                 // nblk x n block products (Vec)
+  int phi_cnt;                 // partials of phi (t_ntiles, or u_nblk when blocked)
   // iteration vectors (Vec = double for float64 storage, float for float32)
   void* r;                     // m
   void* p;                     // n

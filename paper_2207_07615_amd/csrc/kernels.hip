@@ -109,6 +109,7 @@ template <int MODE>
 __device__ __forceinline__ bool spmv_skip(const State* st) {
   if (MODE == MODE_PLAIN) return false;
   if (MODE == MODE_REFINE) return st->final_done || !st->done;
+  if (MODE == MODE_TRANSB) return st->final_done || st->done;
   if (st->final_done || st->done) return true;
   if (MODE == MODE_RESID) return st->k == 0;
   if (MODE == MODE_AP) return st->skip != 0;
@@ -160,21 +161,25 @@ __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
   __shared__ double s_wp[2][kWaves];
 
   const int2 ent = list[blockIdx.x];
+  if (MODE == MODE_TRANSB && ent.y < 0) return;  // padding of the XCD-interleaved list
   const Desc* d = D + ent.x;
   const State* st = d->st;
   if (spmv_skip<MODE>(st)) return;
 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const bool tr = (MODE == MODE_TRANS) || (MODE == MODE_PLAIN && transpose);
-  const int* __restrict__ ptr = tr ? d->t_ptr : d->a_ptr;
-  const int* __restrict__ idx = tr ? d->t_idx : d->a_idx;
-  const Val* __restrict__ val = static_cast<const Val*>(tr ? d->t_val : d->a_val);
-  const int* __restrict__ tile = tr ? d->t_tile : d->a_tile;
-  const int* __restrict__ grp = tr ? d->t_grp : d->a_grp;
+  const int blk = (MODE == MODE_TRANSB) ? (ent.y >> 24) : 0;
+  const int gi = (MODE == MODE_TRANSB) ? (ent.y & 0xFFFFFF) : ent.y;
+  const int* __restrict__ ptr = MODE == MODE_TRANSB ? d->tb_ptr[blk] : (tr ? d->t_ptr : d->a_ptr);
+  const int* __restrict__ idx = MODE == MODE_TRANSB ? d->tb_idx[blk] : (tr ? d->t_idx : d->a_idx);
+  const Val* __restrict__ val =
+      static_cast<const Val*>(MODE == MODE_TRANSB ? d->tb_val[blk] : (tr ? d->t_val : d->a_val));
+  const int* __restrict__ tile = MODE == MODE_TRANSB ? d->tb_tile[blk] : (tr ? d->t_tile : d->a_tile);
+  const int* __restrict__ grp = MODE == MODE_TRANSB ? d->tb_grp[blk] : (tr ? d->t_grp : d->a_grp);
 
   const Vin* __restrict__ xin;
   if (MODE == MODE_RESID) xin = static_cast<const Vin*>(d->p);
-  else if (MODE == MODE_TRANS) xin = static_cast<const Vin*>(d->r);
+  else if (MODE == MODE_TRANS || MODE == MODE_TRANSB) xin = static_cast<const Vin*>(d->r);
   else if (MODE == MODE_REFINE) xin = reinterpret_cast<const Vin*>(d->xo);
   else if (MODE == MODE_PLAIN) xin = static_cast<const Vin*>(d->p);
   else xin = reinterpret_cast<const Vin*>(d->P + (size_t)st->kh * d->n);
@@ -200,6 +205,9 @@ __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
       static_cast<Vec*>(d->y)[i] = Vec(s);
       double ds = double(Vec(s));
       part += d->wi ? ds * ds / d->wi[i] : ds * ds;
+    } else if (MODE == MODE_TRANSB) {
+      using Vec = Vin;
+      static_cast<Vec*>(d->ypart)[(size_t)blk * d->n + i] = Vec(s);
     } else if (MODE == MODE_REFINE) {
       double bi = d->b[i];
       double ri = bi - double(s);
@@ -211,7 +219,7 @@ __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
     }
   };
 
-  const int wt = grp[ent.y * kWaves + w];
+  const int wt = grp[gi * kWaves + w];
   if (wt >= 0) {
     const int r0 = tile[wt], r1 = tile[wt + 1];
     const int e0 = ptr[r0];
@@ -302,7 +310,7 @@ __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
     }
   }
 
-  if (MODE == MODE_PLAIN) return;
+  if (MODE == MODE_PLAIN || MODE == MODE_TRANSB) return;
   part = wave_sum(part);
   if (MODE == MODE_REFINE) part2 = wave_sum(part2);
   if (lane == 0) {
@@ -435,7 +443,7 @@ __global__ __launch_bounds__(kRW) void k_step(const Desc* __restrict__ D, const 
   State* st = d->st;
   if (st->final_done || st->done) return;
   const double rho = big_sum_array(d->part_rho, d->a_ntiles, s_red);
-  const double phi = big_sum_array(d->part_phi, d->t_ntiles, s_red);
+  const double phi = big_sum_array(d->part_phi, d->phi_cnt, s_red);
   const long long k = st->k;
   double theta = 0.0;
   if (k > 0) theta = big_sum_array(d->part_theta, d->u_nblk, s_red);
@@ -704,6 +712,7 @@ void launch_spmv(int mode, bool f32, int V, const Desc* d, const int2* list, int
       case MODE_REFINE: spmv_v<double, double, double, MODE_REFINE>(V, d, list, n, 0, s); break;
       case MODE_PLAIN: spmv_v<double, double, double, MODE_PLAIN>(V, d, list, n, transpose, s); break;
       case MODE_AP: spmv_v<double, double, double, MODE_AP>(V, d, list, n, 0, s); break;
+      case MODE_TRANSB: spmv_v<double, double, double, MODE_TRANSB>(V, d, list, n, 1, s); break;
     }
   } else {
     switch (mode) {
@@ -711,6 +720,7 @@ void launch_spmv(int mode, bool f32, int V, const Desc* d, const int2* list, int
       case MODE_TRANS: spmv_v<float, float, float, MODE_TRANS>(V, d, list, n, 1, s); break;
       case MODE_REFINE: spmv_v<float, double, double, MODE_REFINE>(V, d, list, n, 0, s); break;
       case MODE_PLAIN: spmv_v<float, double, double, MODE_PLAIN>(V, d, list, n, transpose, s); break;
+      case MODE_TRANSB: spmv_v<float, float, float, MODE_TRANSB>(V, d, list, n, 1, s); break;
       default: throw InvalidArg{"mode not available for float32 storage"};
     }
   }
@@ -847,6 +857,118 @@ void launch_check(const double* a, long long n, int positive, int* flag, hipStre
   if (n <= 0) return;
   k_check<<<grid_for(n), kWG, 0, s>>>(a, n, positive, flag);
   PLSS_HIP(hipGetLastError());
+}
+
+}  // namespace plss
+
+namespace plss {
+
+// ------------------------------------------------------------------ row-blocked transpose
+
+// For every column j of the CSC and every row block b (rows [rb[b], rb[b+1])),
+// the number of the column's entries in that block: rows are ascending inside
+// a column, so block b's entries are one contiguous sub-segment.
+__global__ void k_blk_count(const int* __restrict__ cp, const int* __restrict__ ri, int n,
+                            const int* __restrict__ rb, int nblk, int* __restrict__ cnt) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    const int b0 = cp[j], b1 = cp[j + 1];
+    int prev = b0;
+    for (int b = 0; b < nblk; ++b) {
+      // first entry of the column with row >= rb[b + 1]
+      const int lim = rb[b + 1];
+      int lo = prev, hi = b1;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ri[mid] < lim) lo = mid + 1;
+        else hi = mid;
+      }
+      cnt[(size_t)b * n + j] = lo - prev;
+      prev = lo;
+    }
+  }
+}
+
+// Copy block b's sub-segment of every column into that block's arrays:
+// the sub-segment starts after the column's entries of blocks 0..b-1.
+template <class Val>
+__global__ void k_blk_copy(const int* __restrict__ cp, const int* __restrict__ ri, const Val* __restrict__ cv,
+                           int n, int b, const int* __restrict__ bptr, int* __restrict__ oi,
+                           Val* __restrict__ ov) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int nw = (gridDim.x * blockDim.x) >> 6;
+  for (int j = wave; j < n; j += nw) {
+    int src = cp[j];
+    for (int q = 0; q < b; ++q) {
+      const int* p = bptr + (size_t)q * (n + 1);
+      src += p[j + 1] - p[j];
+    }
+    const int* p = bptr + (size_t)b * (n + 1);
+    const int dst = p[j], len = p[j + 1] - p[j];
+    for (int q = lane; q < len; q += 64) {
+      oi[dst + q] = ri[src + q];
+      ov[dst + q] = cv[src + q];
+    }
+  }
+}
+
+// y_j = sum over blocks of the block products (fixed block order); partial phi.
+template <class Vec>
+__global__ __launch_bounds__(kWG) void k_ycomb(const Desc* __restrict__ D, const int2* __restrict__ list) {
+  __shared__ double s_red[kWaves];
+  const int2 ent = list[blockIdx.x];
+  const Desc* d = D + ent.x;
+  const State* st = d->st;
+  if (st->final_done || st->done || d->nblk <= 1) return;
+  const int n = d->n, nb = d->nblk;
+  Vec* __restrict__ y = static_cast<Vec*>(d->y);
+  const Vec* __restrict__ yp = static_cast<const Vec*>(d->ypart);
+  double part = 0.0;
+  const int base = ent.y * (kWG * 4);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = base + u * kWG + threadIdx.x;
+    if (j < n) {
+      Vec s = yp[j];
+      for (int b = 1; b < nb; ++b) s += yp[(size_t)b * n + j];
+      y[j] = s;
+      const double ds = double(s);
+      part += d->wi ? ds * ds / d->wi[j] : ds * ds;
+    }
+  }
+  part = block_sum(part, s_red);
+  if (threadIdx.x == 0) d->part_phi[ent.y] = part;
+}
+
+// counts and per-block pointer arrays (bptr: nblk x (n+1), relative to each block)
+void blk_build(const int* cp, const int* ri, int n, const int* d_rb, int nblk, int* d_cnt, int* d_bptr,
+               void* scan_work, hipStream_t s) {
+  k_blk_count<<<grid_for(n, kWG), kWG, 0, s>>>(cp, ri, n, d_rb, nblk, d_cnt);
+  const int nbk = (n + 1023) / 1024;
+  long long* bsum = static_cast<long long*>(scan_work);
+  for (int b = 0; b < nblk; ++b) {
+    k_scan_blocks<<<nbk, kWG, 0, s>>>(d_cnt + (size_t)b * n, n, bsum);
+    k_scan_top<<<1, 64, 0, s>>>(bsum, nbk);
+    k_scan_apply<<<nbk, kWG, 0, s>>>(d_cnt + (size_t)b * n, n, bsum, d_bptr + (size_t)b * (n + 1));
+  }
+  PLSS_HIP(hipGetLastError());
+}
+
+void blk_copy(const int* cp, const int* ri, const void* cv, bool f32, int n, int b, const int* d_bptr, int* oi,
+              void* ov, hipStream_t s) {
+  if (f32)
+    k_blk_copy<float><<<grid_for((long long)n * 64, kWG), kWG, 0, s>>>(
+        cp, ri, static_cast<const float*>(cv), n, b, d_bptr, oi, static_cast<float*>(ov));
+  else
+    k_blk_copy<double><<<grid_for((long long)n * 64, kWG), kWG, 0, s>>>(
+        cp, ri, static_cast<const double*>(cv), n, b, d_bptr, oi, static_cast<double*>(ov));
+  PLSS_HIP(hipGetLastError());
+}
+
+void launch_ycomb(bool f32, const Desc* d, const int2* ulist, int n, hipStream_t s) {
+  if (n <= 0) return;
+  if (f32) k_ycomb<float><<<n, kWG, 0, s>>>(d, ulist);
+  else k_ycomb<double><<<n, kWG, 0, s>>>(d, ulist);
 }
 
 }  // namespace plss

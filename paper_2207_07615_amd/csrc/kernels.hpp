@@ -39,3 +39,12 @@ int validate_csr_device(const long long* ptr, const int* idx, const double* val,
 namespace plss {
 void launch_check(const double* a, long long n, int positive, int* flag, hipStream_t s);
 }  // namespace plss
+
+namespace plss {
+// row-blocked transpose: counts + per-block pointers, then one copy per block
+void blk_build(const int* cp, const int* ri, int n, const int* d_rb, int nblk, int* d_cnt, int* d_bptr,
+               void* scan_work, hipStream_t s);
+void blk_copy(const int* cp, const int* ri, const void* cv, bool f32, int n, int b, const int* d_bptr, int* oi,
+              void* ov, hipStream_t s);
+void launch_ycomb(bool f32, const Desc* d, const int2* ulist, int n, hipStream_t s);
+}  // namespace plss

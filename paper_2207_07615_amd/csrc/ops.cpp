@@ -129,6 +129,7 @@ void autotune_matrix(plss_handle* h, plss_matrix* A, hipStream_t s) {
     }
     set_tiles(dir, best_v, s);
   }
+  for (int b = 0; b < A->nblk && A->nblk > 1; ++b) set_tiles(A->TB[b], A->T.V, s);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
 }

@@ -168,6 +168,7 @@ plss_matrix* matrix_create(plss_handle* h, const plss_csr* A, plss_dtype storage
     PLSS_HIP(hipStreamSynchronize(s));
     set_tiles(a, 8, s);
     set_tiles(t, 8, s);
+    build_row_blocks(M, s);
   } catch (...) {
     if (d_v64 && d_v64 != M->A.val) dfree(d_v64);
     dfree(d_rp64);
@@ -181,8 +182,9 @@ plss_matrix* matrix_create(plss_handle* h, const plss_csr* A, plss_dtype storage
   dfree(dflag);
   dfree(work);
   h->refs += 1;
-  M->bytes = (size_t)nnz * (vsz + 4) * 2 + sizeof(int) * (size_t)(m + n + 2) +
-             sizeof(int) * (size_t)(M->A.ntiles + M->T.ntiles + 2);
+  M->bytes = (size_t)nnz * (vsz + 4) * (M->nblk > 1 ? 3 : 2) + sizeof(int) * (size_t)(m + n + 2) +
+             sizeof(int) * (size_t)(M->A.ntiles + M->T.ntiles + 2) +
+             (M->nblk > 1 ? sizeof(int) * (size_t)M->nblk * (n + 1) : 0);
   return M;
 }
 
@@ -195,7 +197,72 @@ void matrix_destroy(plss_matrix* M) {
     dfree(d->tile);
     dfree(d->grp);
   }
+  for (int b = 0; b < kMaxBlk; ++b) {
+    PlssDir& d = M->TB[b];
+    dfree(d.idx);
+    dfree(d.val);
+    dfree(d.tile);
+    dfree(d.grp);
+  }
+  dfree(M->tb_ptr_all);
   delete M;
+}
+
+// Row blocks of the transposed store: when the gathered vector r (m
+// entries) is larger than about 3 MB it does not stay in one XCD's 4 MB L2;
+// splitting the rows into 8 blocks of equal nnz gives every XCD a slice of
+// r that does.  Block b holds, column by column, the entries of its rows
+// (a contiguous sub-segment of each CSC column).
+void build_row_blocks(plss_matrix* M, hipStream_t s) {
+  const size_t vb = M->f32 ? 4 : 8;
+  const long long m = M->m, n = M->n, nnz = M->nnz;
+  if ((size_t)m * vb <= (3u << 20) || nnz < 8 * 64) {
+    M->nblk = 1;
+    return;
+  }
+  const int nb = kMaxBlk;
+  M->nblk = nb;
+  // row boundaries balancing the entries
+  const std::vector<int>& rp = M->A.h_ptr;
+  M->rb[0] = 0;
+  int i = 0;
+  for (int b = 1; b < nb; ++b) {
+    const long long target = nnz * b / nb;
+    while (i < m && rp[i] < target) ++i;
+    M->rb[b] = i;
+  }
+  M->rb[nb] = (int)m;
+  int* d_rb = static_cast<int*>(dmalloc(sizeof(int) * (nb + 1)));
+  int* d_cnt = static_cast<int*>(dmalloc(sizeof(int) * (size_t)nb * n));
+  void* work = dmalloc(sizeof(long long) * ((size_t)(n + 1023) / 1024 + 64));
+  try {
+    M->tb_ptr_all = static_cast<int*>(dmalloc(sizeof(int) * (size_t)nb * (n + 1)));
+    PLSS_HIP(hipMemcpyAsync(d_rb, M->rb, sizeof(int) * (nb + 1), hipMemcpyHostToDevice, s));
+    blk_build(M->T.ptr, M->T.idx, (int)n, d_rb, nb, d_cnt, M->tb_ptr_all, work, s);
+    std::vector<int> hp((size_t)nb * (n + 1));
+    PLSS_HIP(hipMemcpyAsync(hp.data(), M->tb_ptr_all, sizeof(int) * hp.size(), hipMemcpyDeviceToHost, s));
+    PLSS_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < nb; ++b) {
+      PlssDir& d = M->TB[b];
+      d.nrows = (int)n;
+      d.ncols = (int)m;
+      d.h_ptr.assign(hp.begin() + (size_t)b * (n + 1), hp.begin() + (size_t)(b + 1) * (n + 1));
+      const long long nz = d.h_ptr[n];
+      d.ptr = M->tb_ptr_all + (size_t)b * (n + 1);
+      d.idx = static_cast<int*>(dmalloc(sizeof(int) * std::max<long long>(nz, 1)));
+      d.val = dmalloc(vb * std::max<long long>(nz, 1));
+      blk_copy(M->T.ptr, M->T.idx, M->T.val, M->f32, (int)n, b, M->tb_ptr_all, d.idx, d.val, s);
+      set_tiles(d, M->T.V, s);
+    }
+  } catch (...) {
+    dfree(d_rb);
+    dfree(d_cnt);
+    dfree(work);
+    throw;
+  }
+  dfree(d_rb);
+  dfree(d_cnt);
+  dfree(work);
 }
 
 void handle_release(plss_handle* h) {

@@ -40,6 +40,12 @@ struct plss_matrix {
   long long m = 0, n = 0, nnz = 0;
   bool f32 = false;
   PlssDir A, T;
+  // row-blocked copy of the transpose (one block per XCD) for the product
+  // with Aᵀ when r does not fit one XCD's L2; nblk = 1 means none
+  int nblk = 1;
+  int rb[plss::kMaxBlk + 1] = {0};
+  PlssDir TB[plss::kMaxBlk];
+  int* tb_ptr_all = nullptr;   // nblk x (n+1) pointers shared by the blocks
   size_t bytes = 0;
 };
 
@@ -58,6 +64,7 @@ void set_tiles(PlssDir& d, int V, hipStream_t s);
 plss_matrix* matrix_create(plss_handle* h, const plss_csr* A, plss_dtype storage, hipStream_t s);
 void matrix_destroy(plss_matrix* A);
 void handle_release(plss_handle* h);  // drop one reference; frees a closed handle at zero
+void build_row_blocks(plss_matrix* M, hipStream_t s);
 size_t matrix_footprint(long long m, long long n, long long nnz, bool f32);
 
 }  // namespace plss

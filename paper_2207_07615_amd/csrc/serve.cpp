@@ -79,18 +79,7 @@ struct plss_server {
   plss::Desc* d_desc = nullptr;
   std::vector<plss::Desc> h_desc;
   std::vector<int> free_slots;
-  char* d_lists = nullptr;
-  char* h_lists = nullptr;
-  size_t lists_cap = 0;
-  struct Group {
-    int key;
-    const int2* list;
-    int n;
-  };
-  std::vector<Group> ga, gt, gu, gaf;
-  const int* d_sys = nullptr;
-  int n_sys = 0;
-  bool any_f32 = false;
+  plss::ListSet lists;
 };
 
 namespace plss {
@@ -120,72 +109,10 @@ void host_validate(const Req& r) {
     if (!std::isfinite(v)) throw InvalidArg{"b has a non-finite entry"};
 }
 
-size_t align64(size_t v) { return (v + 63) / 64 * 64; }
-
 void rebuild_lists(plss_server* S) {
-  std::map<int, std::vector<int2>> la, lt, lu, laf;
-  std::vector<int> ls;
-  S->any_f32 = false;
-  for (Req* r : S->active) {
-    const SysRun& run = *r->run;
-    const int i = r->slot;
-    const int f = run.f32 ? 1 : 0;
-    S->any_f32 |= run.f32;
-    auto& A = la[f * 100 + r->M->A.V];
-    auto& AF = laf[f];
-    for (int t = 0; t < r->M->A.ntiles; ++t) {
-      A.push_back(make_int2(i, t));
-      AF.push_back(make_int2(i, t));
-    }
-    auto& T = lt[f * 100 + r->M->T.V];
-    for (int t = 0; t < r->M->T.ntiles; ++t) T.push_back(make_int2(i, t));
-    auto& U = lu[f];
-    for (int t = 0; t < run.u_nblk; ++t) U.push_back(make_int2(i, t));
-    ls.push_back(i);
-  }
-  size_t total = ls.size() * sizeof(int) + 64;
-  for (auto* mp : {&la, &lt, &lu, &laf})
-    for (auto& kv : *mp) total += kv.second.size() * sizeof(int2) + 64;
-  if (total > S->lists_cap) {
-    dfree(S->d_lists);
-    if (S->h_lists) (void)hipHostFree(S->h_lists);
-    S->lists_cap = total * 2;
-    S->d_lists = static_cast<char*>(dmalloc(S->lists_cap));
-    PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&S->h_lists), S->lists_cap, hipHostMallocDefault));
-  }
-  size_t off = 0;
-  auto put = [&](std::map<int, std::vector<int2>>& mp, std::vector<plss_server::Group>& out) {
-    out.clear();
-    for (auto& kv : mp) {
-      if (kv.second.empty()) continue;
-      std::memcpy(S->h_lists + off, kv.second.data(), kv.second.size() * sizeof(int2));
-      out.push_back({kv.first, reinterpret_cast<const int2*>(S->d_lists + off), (int)kv.second.size()});
-      off = align64(off + kv.second.size() * sizeof(int2));
-    }
-  };
-  put(la, S->ga);
-  put(lt, S->gt);
-  put(lu, S->gu);
-  put(laf, S->gaf);
-  std::memcpy(S->h_lists + off, ls.data(), ls.size() * sizeof(int));
-  S->d_sys = reinterpret_cast<const int*>(S->d_lists + off);
-  S->n_sys = (int)ls.size();
-  off += ls.size() * sizeof(int);
-  PLSS_HIP(hipMemcpyAsync(S->d_lists, S->h_lists, off, hipMemcpyHostToDevice, S->main));
-}
-
-void outer_seq(plss_server* S) {
-  for (auto& g : S->gu) launch_axpy_out(S->d_desc, g.list, g.n, S->main);
-  for (auto& g : S->ga) launch_spmv(MODE_REFINE, g.key >= 100, g.key % 100, S->d_desc, g.list, g.n, 0, S->main);
-  launch_outer(S->d_desc, S->d_sys, S->n_sys, S->main);
-  for (auto& g : S->gaf) launch_start(g.key == 1, S->d_desc, g.list, g.n, S->main);
-}
-
-void iteration(plss_server* S) {
-  for (auto& g : S->ga) launch_spmv(MODE_RESID, g.key >= 100, g.key % 100, S->d_desc, g.list, g.n, 0, S->main);
-  for (auto& g : S->gt) launch_spmv(MODE_TRANS, g.key >= 100, g.key % 100, S->d_desc, g.list, g.n, 1, S->main);
-  launch_step(S->d_desc, S->d_sys, S->n_sys, S->main);
-  for (auto& g : S->gu) launch_update(g.key == 1, S->d_desc, g.list, g.n, S->main);
+  std::vector<std::pair<int, const SysRun*>> items;
+  for (Req* r : S->active) items.push_back({r->slot, r->run.get()});
+  S->lists.build(items, S->main);
 }
 
 // Upload and prepare one request on the side stream (server thread).
@@ -312,13 +239,13 @@ void loop(plss_server* S) {
       if (changed) rebuild_lists(S);
       // one chunk for every admitted system
       const int chunk = 16;
-      const int outer_every = S->any_f32 ? 4 : chunk;
-      outer_seq(S);
+      const int outer_every = S->lists.any_f32 ? 4 : chunk;
+      S->lists.outer_seq(S->d_desc, S->main);
       for (int it = 0; it < chunk; ++it) {
-        if (it > 0 && it % outer_every == 0) outer_seq(S);
-        iteration(S);
+        if (it > 0 && it % outer_every == 0) S->lists.outer_seq(S->d_desc, S->main);
+        S->lists.iteration(S->d_desc, S->main, nullptr);
       }
-      outer_seq(S);
+      S->lists.outer_seq(S->d_desc, S->main);
       PLSS_HIP(hipMemcpyAsync(S->h_slots, S->d_slots, sizeof(State) * S->max_slots, hipMemcpyDeviceToHost, S->main));
       // overlap: admit while the chunk runs
       more = admit(S);
@@ -513,15 +440,13 @@ void server_destroy(plss_server* S) {
   }
   dfree(S->d_slots);
   dfree(S->d_desc);
-  dfree(S->d_lists);
   if (S->h_slots) (void)hipHostFree(S->h_slots);
-  if (S->h_lists) (void)hipHostFree(S->h_lists);
   (void)hipStreamDestroy(S->main);
   (void)hipStreamDestroy(S->side);
-  (void)hipSetDevice(prev);
   plss_handle* h = S->h;
   delete S;
   handle_release(h);
+  (void)hipSetDevice(prev);
 }
 
 }  // namespace plss

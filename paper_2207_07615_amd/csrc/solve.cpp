@@ -50,7 +50,8 @@ void SysRun::setup(const plss_matrix* M, const double* b_in, const plss_opts* o,
   const size_t o_r = take(vs * m), o_p = take(vs * n), o_y = take(vs * n), o_c = f32 ? take(vs * m) : 0;
   const size_t o_wi = o->wi_diag ? take(8 * n) : 0;
   const size_t o_pr = take(8 * M->A.ntiles), o_pb = take(8 * M->A.ntiles);
-  const size_t o_pp = take(8 * M->T.ntiles), o_pt = take(8 * u_nblk);
+  const size_t o_pp = take(8 * (size_t)std::max(M->T.ntiles, u_nblk)), o_pt = take(8 * u_nblk);
+  const size_t o_yp = M->nblk > 1 ? take(vs * n * M->nblk) : 0;
   const size_t o_h = take(8 * (size_t)hist_len);
   arena = static_cast<char*>(dmalloc(off));
   bytes = off;
@@ -72,6 +73,16 @@ void SysRun::setup(const plss_matrix* M, const double* b_in, const plss_opts* o,
   desc.m = (int)m;
   desc.n = (int)n;
   desc.u_nblk = u_nblk;
+  desc.nblk = M->nblk;
+  for (int b = 0; b < M->nblk && M->nblk > 1; ++b) {
+    desc.tb_ptr[b] = M->TB[b].ptr;
+    desc.tb_idx[b] = M->TB[b].idx;
+    desc.tb_val[b] = M->TB[b].val;
+    desc.tb_tile[b] = M->TB[b].tile;
+    desc.tb_grp[b] = M->TB[b].grp;
+  }
+  desc.ypart = M->nblk > 1 ? arena + o_yp : nullptr;
+  desc.phi_cnt = M->nblk > 1 ? u_nblk : M->T.ntiles;
   desc.b = reinterpret_cast<double*>(arena + o_b);
   desc.xo = reinterpret_cast<double*>(arena + o_xo);
   desc.x = f32 ? reinterpret_cast<double*>(arena + o_x) : desc.xo;
@@ -114,32 +125,111 @@ void SysRun::upload(const double* b_in, const double* x0, const double* wi, hipS
 
 // ------------------------------------------------------------------ batch runner
 
-namespace {
-
-struct Lists {
-  // key: (f32, V) for tile lists, f32 for block lists
-  std::map<int, std::vector<int2>> a, t, u;
-  std::vector<int> s;
-  std::map<int, std::vector<int2>> a_f;  // CSR tiles grouped by f32 only (start kernel)
-};
-
-struct DevLists {
-  std::vector<std::pair<int, std::pair<const int2*, int>>> a, t, u, af;
-  const int* s = nullptr;
-  int ns = 0;
-};
-
-}  // namespace
-
 BatchRunner::BatchRunner(plss_handle* h) : h_(h) {}
 
 BatchRunner::~BatchRunner() {
   dfree(d_desc_);
   dfree(d_state_);
-  dfree(d_lists_);
   if (h_state_) (void)hipHostFree(h_state_);
-  if (h_lists_) (void)hipHostFree(h_lists_);
   for (auto e : events_) (void)hipEventDestroy(e);
+}
+
+// ------------------------------------------------------------------ launch lists
+
+ListSet::~ListSet() {
+  dfree(d);
+  if (hbuf) (void)hipHostFree(hbuf);
+}
+
+void ListSet::build(const std::vector<std::pair<int, const SysRun*>>& items, hipStream_t s) {
+  std::map<int, std::vector<int2>> la, lt, lu, laf;
+  std::vector<int> ls;
+  any_f32 = any_blk = false;
+  for (const auto& it : items) {
+    const int i = it.first;
+    const SysRun& r = *it.second;
+    const plss_matrix* M = r.A;
+    const int f = r.f32 ? 1 : 0;
+    any_f32 |= r.f32;
+    auto& A = la[f * 100 + M->A.V];
+    auto& AF = laf[f];
+    for (int t = 0; t < M->A.ntiles; ++t) {
+      A.push_back(make_int2(i, t));
+      AF.push_back(make_int2(i, t));
+    }
+    if (M->nblk > 1) {
+      any_blk = true;
+      auto& T = lt[1000 + f * 100 + M->T.V];
+      int qmax = 0;
+      for (int b = 0; b < M->nblk; ++b) qmax = std::max(qmax, M->TB[b].ntiles);
+      for (int q = 0; q < qmax; ++q)
+        for (int b = 0; b < kMaxBlk; ++b)
+          T.push_back(make_int2(i, (b < M->nblk && q < M->TB[b].ntiles) ? ((b << 24) | q) : -1));
+    } else {
+      auto& T = lt[f * 100 + M->T.V];
+      for (int t = 0; t < M->T.ntiles; ++t) T.push_back(make_int2(i, t));
+    }
+    auto& U = lu[f];
+    for (int t = 0; t < r.u_nblk; ++t) U.push_back(make_int2(i, t));
+    ls.push_back(i);
+  }
+  size_t total = ls.size() * sizeof(int) + 64;
+  for (auto* mp : {&la, &lt, &lu, &laf})
+    for (auto& kv : *mp) total += kv.second.size() * sizeof(int2) + 64;
+  if (total > cap) {
+    dfree(d);
+    d = nullptr;
+    if (hbuf) (void)hipHostFree(hbuf);
+    hbuf = nullptr;
+    cap = total * 2;
+    d = static_cast<char*>(dmalloc(cap));
+    PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&hbuf), cap, hipHostMallocDefault));
+  }
+  // the host buffer may still feed a copy of the previous build
+  PLSS_HIP(hipStreamSynchronize(s));
+  size_t off = 0;
+  auto put = [&](std::map<int, std::vector<int2>>& mp, std::vector<Group>& out) {
+    out.clear();
+    for (auto& kv : mp) {
+      if (kv.second.empty()) continue;
+      std::memcpy(hbuf + off, kv.second.data(), kv.second.size() * sizeof(int2));
+      out.push_back({kv.first, reinterpret_cast<const int2*>(d + off), (int)kv.second.size()});
+      off = align_up(off + kv.second.size() * sizeof(int2), 64);
+    }
+  };
+  put(la, a);
+  put(lt, t);
+  put(lu, u);
+  put(laf, af);
+  std::memcpy(hbuf + off, ls.data(), ls.size() * sizeof(int));
+  sys = reinterpret_cast<const int*>(d + off);
+  nsys = (int)ls.size();
+  off += ls.size() * sizeof(int);
+  PLSS_HIP(hipMemcpyAsync(d, hbuf, off, hipMemcpyHostToDevice, s));
+}
+
+void ListSet::outer_seq(const Desc* dd, hipStream_t s) const {
+  for (auto& g : u) launch_axpy_out(dd, g.list, g.n, s);
+  for (auto& g : a) launch_spmv(MODE_REFINE, g.key >= 100, g.key % 100, dd, g.list, g.n, 0, s);
+  launch_outer(dd, sys, nsys, s);
+  for (auto& g : af) launch_start(g.key == 1, dd, g.list, g.n, s);
+}
+
+void ListSet::iteration(const Desc* dd, hipStream_t s, hipEvent_t* ev) const {
+  if (ev) PLSS_HIP(hipEventRecord(ev[0], s));
+  for (auto& g : a) launch_spmv(MODE_RESID, g.key >= 100, g.key % 100, dd, g.list, g.n, 0, s);
+  if (ev) PLSS_HIP(hipEventRecord(ev[1], s));
+  for (auto& g : t) {
+    const int k = g.key % 1000;
+    launch_spmv(g.key >= 1000 ? MODE_TRANSB : MODE_TRANS, k >= 100, k % 100, dd, g.list, g.n, 1, s);
+  }
+  if (any_blk)
+    for (auto& g : u) launch_ycomb(g.key == 1, dd, g.list, g.n, s);
+  if (ev) PLSS_HIP(hipEventRecord(ev[2], s));
+  launch_step(dd, sys, nsys, s);
+  if (ev) PLSS_HIP(hipEventRecord(ev[3], s));
+  for (auto& g : u) launch_update(g.key == 1, dd, g.list, g.n, s);
+  if (ev) PLSS_HIP(hipEventRecord(ev[4], s));
 }
 
 void BatchRunner::add(const plss_matrix* A, const double* b, const plss_opts* o, long long hist_len) {
@@ -179,76 +269,9 @@ void BatchRunner::prepare(hipStream_t s) {
 }
 
 void BatchRunner::build_lists(const std::vector<int>& active, hipStream_t s) {
-  std::map<int, std::vector<int2>> la, lt, lu, laf;
-  std::vector<int> ls;
-  for (int i : active) {
-    const SysRun& r = *runs_[i];
-    const int f = r.f32 ? 1 : 0;
-    auto& A = la[f * 100 + r.A->A.V];
-    for (int t = 0; t < r.A->A.ntiles; ++t) A.push_back(make_int2(i, t));
-    auto& AF = laf[f];
-    for (int t = 0; t < r.A->A.ntiles; ++t) AF.push_back(make_int2(i, t));
-    auto& T = lt[f * 100 + r.A->T.V];
-    for (int t = 0; t < r.A->T.ntiles; ++t) T.push_back(make_int2(i, t));
-    auto& U = lu[f];
-    for (int t = 0; t < r.u_nblk; ++t) U.push_back(make_int2(i, t));
-    ls.push_back(i);
-  }
-  size_t total = ls.size() * sizeof(int) + 64;
-  for (auto* mp : {&la, &lt, &lu, &laf})
-    for (auto& kv : *mp) total += kv.second.size() * sizeof(int2) + 64;
-  if (total > lists_cap_) {
-    dfree(d_lists_);
-    if (h_lists_) (void)hipHostFree(h_lists_);
-    lists_cap_ = total * 2;
-    d_lists_ = static_cast<char*>(dmalloc(lists_cap_));
-    PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_lists_), lists_cap_, hipHostMallocDefault));
-  }
-  size_t off = 0;
-  groups_a_.clear();
-  groups_t_.clear();
-  groups_u_.clear();
-  groups_af_.clear();
-  auto put = [&](std::map<int, std::vector<int2>>& mp, std::vector<Group>& out) {
-    for (auto& kv : mp) {
-      if (kv.second.empty()) continue;
-      std::memcpy(h_lists_ + off, kv.second.data(), kv.second.size() * sizeof(int2));
-      Group g;
-      g.key = kv.first;
-      g.list = reinterpret_cast<const int2*>(d_lists_ + off);
-      g.n = (int)kv.second.size();
-      out.push_back(g);
-      off = align_up(off + kv.second.size() * sizeof(int2), 64);
-    }
-  };
-  put(la, groups_a_);
-  put(lt, groups_t_);
-  put(lu, groups_u_);
-  put(laf, groups_af_);
-  std::memcpy(h_lists_ + off, ls.data(), ls.size() * sizeof(int));
-  d_sys_ = reinterpret_cast<const int*>(d_lists_ + off);
-  n_sys_ = (int)ls.size();
-  off += ls.size() * sizeof(int);
-  PLSS_HIP(hipMemcpyAsync(d_lists_, h_lists_, off, hipMemcpyHostToDevice, s));
-}
-
-void BatchRunner::outer_seq(hipStream_t s) {
-  for (auto& g : groups_u_) launch_axpy_out(d_desc_, g.list, g.n, s);
-  for (auto& g : groups_a_) launch_spmv(MODE_REFINE, g.key >= 100, g.key % 100, d_desc_, g.list, g.n, 0, s);
-  launch_outer(d_desc_, d_sys_, n_sys_, s);
-  for (auto& g : groups_af_) launch_start(g.key == 1, d_desc_, g.list, g.n, s);
-}
-
-void BatchRunner::iteration(hipStream_t s, hipEvent_t* ev) {
-  if (ev) PLSS_HIP(hipEventRecord(ev[0], s));
-  for (auto& g : groups_a_) launch_spmv(MODE_RESID, g.key >= 100, g.key % 100, d_desc_, g.list, g.n, 0, s);
-  if (ev) PLSS_HIP(hipEventRecord(ev[1], s));
-  for (auto& g : groups_t_) launch_spmv(MODE_TRANS, g.key >= 100, g.key % 100, d_desc_, g.list, g.n, 1, s);
-  if (ev) PLSS_HIP(hipEventRecord(ev[2], s));
-  launch_step(d_desc_, d_sys_, n_sys_, s);
-  if (ev) PLSS_HIP(hipEventRecord(ev[3], s));
-  for (auto& g : groups_u_) launch_update(g.key == 1, d_desc_, g.list, g.n, s);
-  if (ev) PLSS_HIP(hipEventRecord(ev[4], s));
+  std::vector<std::pair<int, const SysRun*>> items;
+  for (int i : active) items.push_back({i, runs_[i].get()});
+  lists_.build(items, s);
 }
 
 void BatchRunner::run(hipStream_t s, bool timing, int chunk_req) {
@@ -278,13 +301,13 @@ void BatchRunner::run(hipStream_t s, bool timing, int chunk_req) {
   PLSS_HIP(hipEventCreate(&t1));
   PLSS_HIP(hipEventRecord(t0, s));
   while (!active.empty()) {
-    outer_seq(s);
+    lists_.outer_seq(d_desc_, s);
     const int c = timing ? std::min(chunk, 128) : chunk;
     for (int it = 0; it < c; ++it) {
-      if (it > 0 && it % outer_every == 0) outer_seq(s);
-      iteration(s, timing ? &events_[5 * it] : nullptr);
+      if (it > 0 && it % outer_every == 0) lists_.outer_seq(d_desc_, s);
+      lists_.iteration(d_desc_, s, timing ? &events_[5 * it] : nullptr);
     }
-    outer_seq(s);
+    lists_.outer_seq(d_desc_, s);
     PLSS_HIP(hipMemcpyAsync(h_state_, d_state_, sizeof(State) * ns, hipMemcpyDeviceToHost, s));
     PLSS_HIP(hipStreamSynchronize(s));
     if (timing) {

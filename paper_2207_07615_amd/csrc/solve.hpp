@@ -26,6 +26,30 @@ struct SysRun {
   void upload(const double* b, const double* x0, const double* wi, hipStream_t s);
 };
 
+// Launch lists of the phase kernels over a set of systems (slot, run):
+// CSR groups and CSC groups keyed by (storage, tile width), update blocks
+// keyed by storage, and the systems.  Row-blocked transposes get a list
+// interleaved so that entry i belongs to block i mod 8 (workgroups are
+// dealt to the 8 XCDs round-robin, so block b's tiles run on XCD b).
+struct ListSet {
+  struct Group {
+    int key;
+    const int2* list;
+    int n;
+  };
+  std::vector<Group> a, t, u, af;
+  const int* sys = nullptr;
+  int nsys = 0;
+  bool any_f32 = false, any_blk = false;
+  char* d = nullptr;
+  char* hbuf = nullptr;
+  size_t cap = 0;
+  ~ListSet();
+  void build(const std::vector<std::pair<int, const SysRun*>>& items, hipStream_t s);
+  void outer_seq(const Desc* dd, hipStream_t s) const;
+  void iteration(const Desc* dd, hipStream_t s, hipEvent_t* ev) const;
+};
+
 class BatchRunner {
  public:
   explicit BatchRunner(plss_handle* h);
@@ -44,14 +68,7 @@ class BatchRunner {
     plss_opts o;
     long long hist_len;
   };
-  struct Group {
-    int key;
-    const int2* list;
-    int n;
-  };
   void build_lists(const std::vector<int>& active, hipStream_t s);
-  void outer_seq(hipStream_t s);
-  void iteration(hipStream_t s, hipEvent_t* ev);
 
   plss_handle* h_;
   std::vector<Item> items_;
@@ -59,12 +76,7 @@ class BatchRunner {
   Desc* d_desc_ = nullptr;
   State* d_state_ = nullptr;
   State* h_state_ = nullptr;
-  char* d_lists_ = nullptr;
-  char* h_lists_ = nullptr;
-  size_t lists_cap_ = 0;
-  std::vector<Group> groups_a_, groups_t_, groups_u_, groups_af_;
-  const int* d_sys_ = nullptr;
-  int n_sys_ = 0;
+  ListSet lists_;
   std::vector<hipEvent_t> events_;
   float elapsed_ms_ = 0;
 };

@@ -209,3 +209,30 @@ def test_batch_equals_alone(h):
         assert inf["status"] == 0
         ref, spread = order_spread(s.A, s.b, inf["iters"])
         assert rel(x, ref.x) <= max(1e-10, 4 * spread)
+
+
+@pytest.mark.parametrize("storage,m", [("f64", 500_000), ("f32", 800_000)])
+def test_row_blocked_transpose(h, storage, m):
+    """Past ~3 MB of r the product with Aᵀ runs on a row-blocked copy of the
+    transpose (one block per XCD); the first iterates match the oracle and
+    the full solve meets the tolerance."""
+    import paper_2207_07615_amd as plss
+    say("row-blocked", storage, m)
+    dt = np.float32 if storage == "f32" else np.float64
+    sysm = gen.large(m=m, n=m // 4, storage=dt)
+    M = matrix(h, sysm.A, storage)
+    assert M.info()["device_bytes"] > 3 * sysm.A.nnz * (8 if storage == "f32" else 12)
+    if storage == "f64":
+        x, info, _ = plss.solve(h, M, sysm.b, tol=1e-300, maxit=12)
+        ref = O.plss_residual(sysm.A, sysm.b, tol=1e-300, maxit=12)
+        assert rel(x, ref.x) <= 1e-12
+        x, info, _ = plss.solve(h, M, sysm.b, tol=1e-8, maxit=1000)
+        assert info["status"] == 0 and info["relres_true"] <= 1.5e-8
+    else:
+        x, info, _ = plss.solve(h, M, sysm.b, tol=1e-8, maxit=4000, refine=True)
+        assert info["status"] == 0 and info["relres_true"] <= 1e-8
+        assert rel(x, sysm.xstar) <= 1e-6
+    cp, ri, va = M.csc()
+    ocp, ori, ova = osp.csr_to_csc(sysm.A.m, sysm.A.n, sysm.A.row_ptr, sysm.A.col_idx, sysm.A.vals)
+    np.testing.assert_array_equal(cp, ocp)
+    np.testing.assert_array_equal(ri, ori)
