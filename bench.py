@@ -14,6 +14,7 @@ on a bounded sample, and the float32-storage + float64-refinement arm of the
 same system (timed separately after the main region).
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
+    python bench.py --config small|underdet|batch|multi|serve   (other workloads)
 """
 from __future__ import annotations
 
@@ -68,6 +69,269 @@ def cpu_baseline(sysm, iters=12):
                       f"({dt:.1f} s, SciPy CSR products, 1 thread)"}
 
 
+def _gen_batch(i):
+    import plss_inputs as gen
+    import numpy as np
+    s = gen.batch_systems(1, first=i)[0]
+    A32 = s.A.astype(np.float32)
+    return A32, gen.rhs(A32, s.xstar), s.xstar
+
+
+def _gen_stream(i):
+    import plss_inputs as gen
+    import numpy as np
+    s = gen.stream_systems(1, first=i)[0]
+    A32 = s.A.astype(np.float32)
+    return s, A32, gen.rhs(A32, s.xstar)
+
+
+def _pool_map(fn, items):
+    import concurrent.futures as cf
+    workers = min(16, os.cpu_count() or 4)
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(fn, items, chunksize=1))
+
+
+def base_line(metric, value, unit, steps, warmup, wall, dtype, config, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": steps,
+           "warmup": warmup, "ms_per_step": 1e3 * wall / max(1, steps), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic (seeded; stands in for the paper's datasets)", "config": config}
+    out.update(extra)
+    return out
+
+
+def kernel_roofline(kms, kn, bm, kind="spmv"):
+    avg = [kms[q] / max(1, kn[q]) for q in range(4)]
+    dom = 0 if avg[0] >= avg[1] else 1
+    dom_bytes = bm["spmv"] if dom == 0 else bm["spmvt"]
+    ach = dom_bytes / (avg[dom] * 1e-3) / 1e9 if avg[dom] > 0 else 0.0
+    return avg, {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                 "kernel": ("product with A" if dom == 0 else "product with Aᵀ") + f" ({kind})",
+                 "algorithmic_bytes_per_launch": dom_bytes}
+
+
+def run_small(args):
+    """2000 x 1000, 8 nnz per row, FP64, tol 1e-8 (cache-resident: the
+    roofline fraction can exceed what HBM alone allows)."""
+    import numpy as np
+    import paper_2207_07615_amd as plss
+    import plss_inputs as gen
+    from oracle import plss as O
+    sysm = gen.small()
+    A = sysm.A
+    h = plss.Handle(0)
+    M = plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n))
+    kw = dict(tol=1e-8, maxit=1000)
+    for _ in range(args.warmup):
+        plss.solve(h, M, sysm.b, **kw)
+    plss.kernel_times(h)
+    lat, its = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        x, info, _ = plss.solve(h, M, sysm.b, timing=True, **kw)
+        lat.append(time.perf_counter() - ts)
+        its.append(info["iters"])
+    wall = time.perf_counter() - t0
+    kms, kn = plss.kernel_times(h)
+    avg, roof = kernel_roofline(kms, kn, bytes_model(A.m, A.n, A.nnz))
+    t1 = time.perf_counter()
+    ref = O.plss_residual(A, sysm.b, tol=1e-8, maxit=1000)
+    tc = time.perf_counter() - t1
+    lat = sorted(1e3 * v for v in lat)
+    return base_line(METRIC, sum(its) / wall, "iters/s", args.steps, args.warmup, wall, "f64",
+                     {"workload": "small: 2000 x 1000 CSR, 8 nnz/row, N(0,1), residual sketch, FP64, tol 1e-8",
+                      "m": A.m, "n": A.n, "nnz": A.nnz},
+                     solves_per_s=args.steps / wall, iters_per_solve=sum(its) / len(its),
+                     p50_ms=lat[len(lat) // 2], p99_ms=lat[-1], relres_true=info["relres_true"],
+                     kernel_ms=dict(zip(["spmv", "spmvt", "step", "update"], avg)), roofline=roof,
+                     rel_err_vs_oracle=float(np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)),
+                     cpu_baseline={"value": ref.iters / tc, "unit": "iters/s", "cores": 1, "kind": "oracle",
+                                   "sample": f"full solve ({ref.iters} iterations, {tc:.2f} s)"})
+
+
+def run_underdet(args):
+    """200,000 x 1,000,000, 30 nnz per row, U(-1,1), mixed sketch, FP64."""
+    import numpy as np
+    import paper_2207_07615_amd as plss
+    import plss_inputs as gen
+    from oracle import plss as O
+    sysm = gen.underdet()
+    A = sysm.A
+    h = plss.Handle(0)
+    M = plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n))
+    kw = dict(sketch="mixed", tol=1e-8, maxit=2000, row_perm=sysm.perm, hist_cap=128)
+    for _ in range(args.warmup):
+        plss.solve(h, M, sysm.b, **kw)
+    its = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x, info, _ = plss.solve(h, M, sysm.b, **kw)
+        its.append(info["iters"])
+    wall = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    ref = O.plss_columns(A, sysm.b, "mixed", perm=sysm.perm, tol=1e-300, maxit=8, hist_cap=128)
+    tc = time.perf_counter() - t1
+    x8, i8, _ = plss.solve(h, M, sysm.b, sketch="mixed", tol=1e-300, maxit=8, row_perm=sysm.perm, hist_cap=128)
+    return base_line(METRIC, sum(its) / wall, "updates/s", args.steps, args.warmup, wall, "f64",
+                     {"workload": "underdet: 200,000 x 1,000,000 CSR, 30 nnz/row, U(-1,1), mixed sketch "
+                                  "(residual + identity columns), FP64, tol 1e-8",
+                      "m": A.m, "n": A.n, "nnz": A.nnz, "hist_cap": 128},
+                     solves_per_s=args.steps / wall, updates_per_solve=sum(its) / len(its),
+                     relres_true=info["relres_true"], status=info["status_name"],
+                     rel_err_vs_oracle_8_updates=float(np.linalg.norm(x8 - ref.x) / np.linalg.norm(ref.x)),
+                     cpu_baseline={"value": ref.iters / tc, "unit": "updates/s", "cores": 1, "kind": "oracle",
+                                   "sample": f"first {ref.iters} column steps ({tc:.1f} s)"})
+
+
+def run_batch(args):
+    """256 uneven systems, FP32 storage + FP64 refinement to 1e-8, one launch
+    per phase over all unfinished systems."""
+    import numpy as np
+    import paper_2207_07615_amd as plss
+    t0 = time.perf_counter()
+    data = _pool_map(_gen_batch, range(args.nsys))
+    log(f"generated {len(data)} systems in {time.perf_counter() - t0:.1f}s, "
+        f"nnz total {sum(d[0].nnz for d in data)}")
+    h = plss.Handle(0)
+    mats = [plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n), storage="f32") for A, _, _ in data]
+    bs = [b for _, b, _ in data]
+    kw = dict(tol=1e-8, maxit=args.maxit_cap, refine=True, inner_tol=1e-4)
+    plss.kernel_times(h)
+    t1 = time.perf_counter()
+    xs, infos = plss.solve_batch(h, mats, bs, timing=True, **kw)
+    wall = time.perf_counter() - t1
+    kms, kn = plss.kernel_times(h)
+    ok = sum(1 for i in infos if i["status"] == 0)
+    errs = [float(np.linalg.norm(x - d[2]) / np.linalg.norm(d[2])) for x, d in zip(xs, data)]
+    tot_nnz = sum(d[0].nnz for d in data)
+    # one system at a time, plain float64 Algorithm 1, same GPU (baseline)
+    sub = list(range(0, len(data), max(1, len(data) // 16)))
+    t2 = time.perf_counter()
+    for i in sub:
+        A, b, xs_ = data[i]
+        M64 = plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n))
+        plss.solve(h, M64, b, tol=1e-8, maxit=args.maxit_cap)
+        del M64
+    t_plain = (time.perf_counter() - t2) / len(sub) * len(data)
+    return base_line(METRIC, len(data) / wall, "solves/s", 1, 0, wall, "f32+f64",
+                     {"workload": f"batch: {len(data)} systems, m log-U[1e3,2e5], n=m*U(.5,1), 5-50 nnz/row, "
+                                  "FP32 storage + FP64 refinement, tol 1e-8", "nnz_total": tot_nnz,
+                      "maxit": args.maxit_cap},
+                     converged=ok, max_rel_err_vs_xstar=max(errs),
+                     iters_total=sum(i["iters"] for i in infos),
+                     kernel_ms_total=dict(zip(["spmv", "spmvt", "step", "update"], kms)),
+                     plain_fp64_one_at_a_time_s=t_plain, speedup_vs_plain_fp64=t_plain / wall)
+
+
+def run_multi(args):
+    """Shared 500,000 x 250,000 (20 nnz/row) with 32 right-hand sides, block
+    products, FP32 storage + FP64 refinement to 1e-8."""
+    import numpy as np
+    import paper_2207_07615_amd as plss
+    import plss_inputs as gen
+    A, B, X = gen.shared_multi_rhs(storage=np.float32)
+    h = plss.Handle(0)
+    M = plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n), storage="f32")
+    kw = dict(tol=1e-8, maxit=5000, refine=True, inner_tol=1e-4)
+    for _ in range(args.warmup):
+        plss.solve_multi(h, M, B.T, **kw)
+    plss.kernel_times(h)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        Xg, infos = plss.solve_multi(h, M, B.T, timing=True, **kw)
+    wall = time.perf_counter() - t0
+    kms, kn = plss.kernel_times(h)
+    nrhs = B.shape[0]
+    # block bytes per iteration: matrix once for all columns (float32 values + int32 index)
+    per_spmm = 8 * A.nnz + 4 * A.m + nrhs * 4 * (2 * A.m + A.n)
+    avg = [kms[q] / max(1, kn[q]) for q in range(4)]
+    ach = per_spmm / (avg[0] * 1e-3) / 1e9
+    errs = [float(np.linalg.norm(Xg[:, c] - X[c]) / np.linalg.norm(X[c])) for c in range(nrhs)]
+    # same right-hand sides one at a time, plain float64 Algorithm 1
+    M64 = plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n))
+    t1 = time.perf_counter()
+    for c in range(4):
+        plss.solve(h, M64, B[c], tol=1e-8, maxit=5000)
+    t_plain = (time.perf_counter() - t1) / 4 * nrhs
+    return base_line(METRIC, args.steps * nrhs / wall, "solves/s", args.steps, args.warmup, wall, "f32+f64",
+                     {"workload": "multi: shared 500,000 x 250,000 CSR, 20 nnz/row, 32 RHS block, "
+                                  "FP32 storage + FP64 refinement, tol 1e-8", "nnz": A.nnz, "nrhs": nrhs},
+                     iters_per_rhs=sum(i["iters"] for i in infos) / nrhs,
+                     max_rel_err_vs_xstar=max(errs), converged=sum(1 for i in infos if i["status"] == 0),
+                     kernel_ms=dict(zip(["spmm", "spmmt", "step", "update"], avg)),
+                     roofline={"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": "block product with A",
+                               "algorithmic_bytes_per_launch": per_spmm},
+                     plain_fp64_one_rhs_at_a_time_s=t_plain, speedup_vs_plain_fp64=t_plain / (wall / args.steps))
+
+
+def run_serve(args):
+    """Served stream: systems with Poisson arrivals, FP32 storage + FP64
+    refinement under continuous batching, against plain per-system FP64."""
+    import numpy as np
+    import paper_2207_07615_amd as plss
+    import plss_inputs as gen
+    t0 = time.perf_counter()
+    data = _pool_map(_gen_stream, range(args.nsys))
+    log(f"generated {len(data)} systems in {time.perf_counter() - t0:.1f}s")
+    h = plss.Handle(0)
+    budget = 200 << 30
+
+    def serve(arrivals):
+        srv = plss.Server(h, hbm_budget_bytes=budget, max_slots=256)
+        t_start = time.perf_counter()
+        reqs = []
+        for (s, A32, b32), ta in zip(data, arrivals):
+            while time.perf_counter() - t_start < ta:
+                time.sleep(0.0005)
+            reqs.append(srv.submit(A32, b32, storage="f32", tol=s.tol,
+                                   maxit=min(s.A.n + 1000, args.maxit_cap), refine=True, inner_tol=1e-4))
+        res = []
+        pending = list(range(len(reqs)))
+        got = {}
+        while pending:
+            nxt = []
+            for i in pending:
+                r = srv.poll(reqs[i])
+                if r is None:
+                    nxt.append(i)
+                else:
+                    got[i] = r
+            pending = nxt
+            time.sleep(0.0005)
+        wall = time.perf_counter() - t_start
+        srv.close()
+        return wall, [got[i] for i in range(len(reqs))]
+
+    n = len(data)
+    wall_sat, res_sat = serve([0.0] * n)
+    rate = 0.7 * n / wall_sat
+    arr = gen.poisson_arrivals(n, rate)
+    wall_p, res_p = serve(list(arr))
+    lat = sorted(info["ms"] for _, info in res_p)
+    conv = sum(1 for _, info in res_sat if info["status"] == 0)
+    # plain per-system FP64 Algorithm 1 on the same GPU, one at a time
+    t1 = time.perf_counter()
+    for s, _, _ in data:
+        M64 = plss.Matrix(h, s.A.row_ptr, s.A.col_idx, s.A.vals, shape=(s.A.m, s.A.n))
+        plss.solve(h, M64, s.b, tol=s.tol, maxit=min(s.A.n + 1000, args.maxit_cap))
+        del M64
+    t_plain = time.perf_counter() - t1
+    return base_line(METRIC, n / wall_sat, "solves/s", 1, 0, wall_sat, "f32+f64",
+                     {"workload": f"serve: {n} systems of the stream recipe (m log-U[1e3,1e6], n/m U(.3,1), "
+                                  "Zipf(1.5) rows clipped to [1,100], tol 1e-6 or 1e-10), FP32 + FP64 refinement, "
+                                  "continuous batching", "nnz_total": sum(s.A.nnz for s, _, _ in data),
+                      "maxit": f"min(n + 1000, {args.maxit_cap})"},
+                     saturated_solves_per_s=n / wall_sat, poisson_rate=rate,
+                     poisson_solves_per_s=n / wall_p, p50_ms=lat[len(lat) // 2],
+                     p99_ms=lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
+                     converged=conv, plain_fp64_solves_per_s=n / t_plain,
+                     speedup_vs_plain_fp64=(n / wall_sat) / (n / t_plain))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -80,11 +344,23 @@ def main():
     ap.add_argument("--autotune", action="store_true", help="pick tile widths by measurement")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (calibrates profiler byte counters)")
+    ap.add_argument("--config", default="large",
+                    choices=["large", "small", "underdet", "batch", "multi", "serve"])
+    ap.add_argument("--nsys", type=int, default=0, help="systems for batch/serve (default 256 / 100)")
+    ap.add_argument("--maxit-cap", type=int, default=4000,
+                    help="batch/serve: iteration bound min(n + 1000, cap) per system")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
+    if args.config != "large":
+        if not args.nsys:
+            args.nsys = 256 if args.config == "batch" else 100
+        fn = {"small": run_small, "underdet": run_underdet, "batch": run_batch,
+              "multi": run_multi, "serve": run_serve}[args.config]
+        print(json.dumps(fn(args)), flush=True)
+        return
 
     import numpy as np
     import torch
@@ -125,9 +401,11 @@ def main():
     kms, kn = plss.kernel_times(h)
     relres_true = info["relres_true"]
     if args.calib_copy:
-        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)  # 1 GiB
+        # an elementwise kernel that reads 1 GiB and writes 1 GiB
+        src = torch.ones(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
         for _ in range(2):
-            dst = src.clone()
+            torch.mul(src, 2.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
     err_xstar = float(torch.linalg.norm(x - torch.from_numpy(sysm.xstar).to(dev)) /
