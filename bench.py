@@ -50,6 +50,25 @@ def bytes_model(m, n, nnz, f32=False):
     return {"spmv": spmv, "spmvt": spmvt, "update": upd, "iter": spmv + spmvt + upd}
 
 
+def recorded_traffic(kernel_index):
+    """Calibrated HBM bytes per launch of the dominant kernel from the
+    committed rocprofv3 counter passes, or None when the kernel source has
+    changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "large_fp64_traffic.txt")
+    src = os.path.join(ROOT, "paper_2207_07615_amd", "csrc", "kernels.hip")
+    try:
+        kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
+        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
+        if kv.get("kernels_hip_sha1_12") != sha:
+            return None
+        sfx = "" if kernel_index == 0 else "_t"
+        return (float(kv["fetch_kib" + sfx]) * float(kv["fetch_scale"]) +
+                float(kv["write_kib" + sfx]) * float(kv["write_scale"])) * 1024.0
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(sysm, iters=12):
     """The oracle (Algorithm 1 in float64, SciPy sparse products) on the
     first `iters` iterations of the same system, single-threaded."""
@@ -447,7 +466,7 @@ def main():
         "relres_true": relres_true,
         "rel_err_vs_xstar": err_xstar,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(dom),
                      "kernel": "spmv (r -= A p, rho)" if dom == 0 else "spmvt (y = A^T r, phi)",
                      "algorithmic_bytes_per_launch": dom_bytes},
     }

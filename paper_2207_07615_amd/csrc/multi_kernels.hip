@@ -99,8 +99,17 @@ __global__ __launch_bounds__(256) void k_spmm(const MDesc* __restrict__ d) {
 __device__ void col_sums(const double* __restrict__ part, int nb, int s, double* s_tmp, double* out) {
   const int sub = threadIdx.x / s, c = threadIdx.x % s, nsub = kMW / s;
   double v = 0.0;
-  if (sub < nsub)
-    for (int b = sub; b < nb; b += nsub) v += part[(size_t)b * s + c];
+  if (sub < nsub) {
+    // 8 independent partial sums in flight, combined in a fixed order
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int b = sub;
+    for (; b + 7 * nsub < nb; b += 8 * nsub) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] += part[(size_t)(b + u * nsub) * s + c];
+    }
+    for (; b < nb; b += nsub) a[0] += part[(size_t)b * s + c];
+    v = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+  }
   __syncthreads();
   if (sub < nsub) s_tmp[sub * s + c] = v;
   __syncthreads();
