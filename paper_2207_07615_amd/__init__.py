@@ -152,6 +152,20 @@ class Matrix:
         _check(_clib().plss_matrix_autotune(self.handle.h, self.A, C.byref(a), C.byref(t)))
         return a.value, t.value
 
+    def layout(self, a_stripes=None, t_stripes=None, unit_rows=0):
+        """Read the product layout, or change it when a_stripes / t_stripes is
+        given: {"a_stripes": bool, "t_stripes": bool, "unit_rows": int}."""
+        got = L.plss_layout()
+        if a_stripes is None and t_stripes is None:
+            _check(_clib().plss_matrix_layout(self.handle.h, self.A, None, C.byref(got)))
+        else:
+            cur = self.layout()
+            want = L.plss_layout(int(cur["a_stripes"] if a_stripes is None else bool(a_stripes)),
+                                 int(cur["t_stripes"] if t_stripes is None else bool(t_stripes)),
+                                 int(unit_rows))
+            _check(_clib().plss_matrix_layout(self.handle.h, self.A, C.byref(want), C.byref(got)))
+        return {"a_stripes": bool(got.a_stripes), "t_stripes": bool(got.t_stripes), "unit_rows": got.unit_rows}
+
     def close(self):
         if self.A:
             _clib().plss_matrix_destroy(self.A)

@@ -33,6 +33,10 @@ class plss_info(C.Structure):
                 ("relres_true", C.c_double), ("status", C.c_int32), ("ms", C.c_double)]
 
 
+class plss_layout(C.Structure):
+    _fields_ = [("a_stripes", C.c_int32), ("t_stripes", C.c_int32), ("unit_rows", C.c_int32)]
+
+
 EXPORTS = {
     # name: (restype, argtypes)
     "plss_opts_default": (None, [C.POINTER(plss_opts)]),
@@ -43,6 +47,7 @@ EXPORTS = {
     "plss_matrix_info": (C.c_int, [C.c_void_p] + [C.POINTER(C.c_int64)] * 4),
     "plss_matrix_csc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "plss_matrix_autotune": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "plss_matrix_layout": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(plss_layout), C.POINTER(plss_layout)]),
     "plss_spmv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "plss_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(plss_opts), C.c_void_p,
                              C.c_void_p, C.c_int64, C.POINTER(plss_info)]),

@@ -24,6 +24,7 @@ SOURCES = [
     "kernels.hip",
     "sketch_kernels.hip",
     "multi_kernels.hip",
+    "stripe.hip",
     "runtime.cpp",
     "solve.cpp",
     "ops.cpp",

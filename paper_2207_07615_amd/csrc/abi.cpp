@@ -181,6 +181,31 @@ plss_status plss_matrix_autotune(plss_handle* h, plss_matrix* A, int32_t* wa, in
   PLSS_GUARD_END
 }
 
+plss_status plss_matrix_layout(plss_handle* h, plss_matrix* A, const plss_layout* want, plss_layout* got) {
+  PLSS_GUARD_BEGIN
+  if (!h || !A) throw InvalidArg{"null handle or matrix"};
+  DeviceScope ds(h->device);
+  std::lock_guard<std::mutex> lk(h->mu);
+  auto report = [&]() {
+    if (got) {
+      got->a_stripes = A->a_striped ? 1 : 0;
+      got->t_stripes = A->t_striped ? 1 : 0;
+      got->unit_rows = A->a_striped ? A->SA.unit_rows : (A->t_striped ? A->SB[0].unit_rows : 0);
+    }
+  };
+  if (want) {
+    try {
+      matrix_set_layout(A, want->a_stripes != 0, want->t_stripes != 0, want->unit_rows, h->stream);
+    } catch (...) {
+      report();
+      throw;
+    }
+  }
+  report();
+  return PLSS_OK;
+  PLSS_GUARD_END
+}
+
 plss_status plss_spmv(plss_handle* h, const plss_matrix* A, int transpose, const double* x, double* y) {
   PLSS_GUARD_BEGIN
   if (!h || !A || !x || !y) throw InvalidArg{"null argument"};

@@ -39,6 +39,24 @@ enum SpmvMode : int {
 
 constexpr int kMaxBlk = 8;         // row blocks of the transposed store (one per XCD)
 
+// Striped store (stripe.hip): a work unit of at most kRBmax rows keeps its
+// row sums in LDS while the gathered vector passes through LDS in stripes
+// of kSW entries; kSThreads threads per unit.
+constexpr int kSW = 4096;
+constexpr int kRBmax = 8192;
+constexpr int kSThreads = 1024;
+constexpr int kMaxStripes = 8192;  // stripes per store (cursor table of the builder in LDS)
+
+struct StripeView {
+  const unsigned* pk;          // entries: (row in unit) << 16 | (column in stripe)
+  const void* val;             // values (storage precision)
+  const int* urow;             // nunits + 1 row starts of the units
+  const int* seg;              // nunits * S + 1 entry starts of the (unit, stripe) segments
+  const int* wsp;              // 16 row-aligned wave starts per segment
+  int nunits, S;
+  int colbase, ncols;          // columns [colbase, colbase + ncols) of the gathered vector
+};
+
 struct State {
   // Algorithm 1 scalars (float64 always)
   double rho, phi, theta, beta, gamma;
@@ -100,6 +118,12 @@ struct Desc {
   const int* tb_grp[kMaxBlk];
   void* ypart;                 // nblk x n block products (Vec)
   int phi_cnt;                 // partials of phi (t_ntiles, or u_nblk when blocked)
+  // striped stores (used instead of the tiles when set)
+  int a_striped;               // products with A (r update, refinement residual)
+  int t_striped;               // block products with Aᵀ (needs nblk > 1)
+  int rho_cnt;                 // partials of rho and ||b||^2 (a_ntiles, or sa.nunits)
+  StripeView sa;
+  StripeView sb[kMaxBlk];
   // iteration vectors (Vec = double for float64 storage, float for float32)
   void* r;                     // m
   void* p;                     // n

@@ -359,8 +359,8 @@ __global__ __launch_bounds__(kRW) void k_outer(const Desc* __restrict__ D, const
   const Desc* d = D + sys[blockIdx.x];
   State* st = d->st;
   if (st->final_done || !st->done) return;
-  const double rr = big_sum_array(d->part_rho, d->a_ntiles, s_red);
-  const double bb = big_sum_array(d->part_b, d->a_ntiles, s_red);
+  const double rr = big_sum_array(d->part_rho, d->rho_cnt, s_red);
+  const double bb = big_sum_array(d->part_b, d->rho_cnt, s_red);
   if (threadIdx.x != 0) return;
   const double nu = sqrt(rr);
   if (st->outer == 0) st->nb_out = sqrt(bb);
@@ -400,7 +400,8 @@ __global__ __launch_bounds__(kRW) void k_outer(const Desc* __restrict__ D, const
   st->outer += 1;
 }
 
-// r <- c (inner right-hand side), partial rho and ||c||^2, on the CSR tiles.
+// r <- c (inner right-hand side), partial rho and ||c||^2, on the row
+// partition of the partials: the CSR tiles, or the units of a striped store.
 template <class Vec>
 __global__ __launch_bounds__(kWG) void k_start(const Desc* __restrict__ D, const int2* __restrict__ list) {
   __shared__ double s_wp[kWaves];
@@ -409,19 +410,28 @@ __global__ __launch_bounds__(kWG) void k_start(const Desc* __restrict__ D, const
   const State* st = d->st;
   if (st->final_done || st->done || st->k != 0) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wt = d->a_grp[ent.y * kWaves + w];
   const double inv = d->is_f32 ? 1.0 / st->nu : 1.0;
   Vec* r = static_cast<Vec*>(d->r);
   Vec* c = static_cast<Vec*>(d->c);
   double part = 0.0;
-  if (wt >= 0) {
-    const int r0 = d->a_tile[wt], r1 = d->a_tile[wt + 1];
-    for (int i = r0 + lane; i < r1; i += 64) {
-      const Vec ci = Vec(d->r64[i] * inv);
-      r[i] = ci;
-      if (c) c[i] = ci;
-      part += double(ci) * double(ci);
+  int r0 = 0, r1 = 0, i0 = lane, step = 64;
+  if (d->a_striped) {
+    r0 = d->sa.urow[ent.y];
+    r1 = d->sa.urow[ent.y + 1];
+    i0 = threadIdx.x;
+    step = kWG;
+  } else {
+    const int wt = d->a_grp[ent.y * kWaves + w];
+    if (wt >= 0) {
+      r0 = d->a_tile[wt];
+      r1 = d->a_tile[wt + 1];
     }
+  }
+  for (int i = r0 + i0; i < r1; i += step) {
+    const Vec ci = Vec(d->r64[i] * inv);
+    r[i] = ci;
+    if (c) c[i] = ci;
+    part += double(ci) * double(ci);
   }
   part = wave_sum(part);
   if (lane == 0) s_wp[w] = part;
@@ -442,13 +452,13 @@ __global__ __launch_bounds__(kRW) void k_step(const Desc* __restrict__ D, const 
   const Desc* d = D + sys[blockIdx.x];
   State* st = d->st;
   if (st->final_done || st->done) return;
-  const double rho = big_sum_array(d->part_rho, d->a_ntiles, s_red);
+  const double rho = big_sum_array(d->part_rho, d->rho_cnt, s_red);
   const double phi = big_sum_array(d->part_phi, d->phi_cnt, s_red);
   const long long k = st->k;
   double theta = 0.0;
   if (k > 0) theta = big_sum_array(d->part_theta, d->u_nblk, s_red);
   double nbi = 0.0;
-  if (k == 0) nbi = big_sum_array(d->part_b, d->a_ntiles, s_red);
+  if (k == 0) nbi = big_sum_array(d->part_b, d->rho_cnt, s_red);
   if (threadIdx.x != 0) return;
 
   if (k == 0) {
@@ -969,6 +979,21 @@ void launch_ycomb(bool f32, const Desc* d, const int2* ulist, int n, hipStream_t
   if (n <= 0) return;
   if (f32) k_ycomb<float><<<n, kWG, 0, s>>>(d, ulist);
   else k_ycomb<double><<<n, kWG, 0, s>>>(d, ulist);
+}
+
+void scan_counts(const int* cnt, int n, int* out, void* work, hipStream_t s) {
+  long long* bsum = static_cast<long long*>(work);
+  if (n <= 0) {
+    k_scan_top<<<1, 64, 0, s>>>(bsum, 0);
+    k_ptr64_to_32<<<1, 64, 0, s>>>(bsum, 1, out);
+    PLSS_HIP(hipGetLastError());
+    return;
+  }
+  const int nbk = (n + 1023) / 1024;
+  k_scan_blocks<<<nbk, kWG, 0, s>>>(cnt, n, bsum);
+  k_scan_top<<<1, 64, 0, s>>>(bsum, nbk);
+  k_scan_apply<<<nbk, kWG, 0, s>>>(cnt, n, bsum, out);
+  PLSS_HIP(hipGetLastError());
 }
 
 }  // namespace plss

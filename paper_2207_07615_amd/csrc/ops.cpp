@@ -52,11 +52,53 @@ void plain_launch(const plss_matrix* A, bool transpose, const double* dx, double
 }
 }  // namespace
 
+// Plain product through a striped store: A x from the store of A, or Aᵀ x
+// as the fixed-order sum of the row blocks' products.
+static void stripe_plain(const plss_matrix* A, bool transpose, const double* dx, double* dy, Scratch& sc,
+                         hipStream_t s) {
+  Desc d{};
+  d.m = (int)A->m;
+  d.n = (int)A->n;
+  d.p = const_cast<double*>(dx);
+  d.r64 = dy;
+  std::vector<int2> l;
+  double* yp = nullptr;
+  if (!transpose) {
+    fill_stripe_view(A->SA, &d.sa);
+    for (int u = 0; u < A->SA.nunits; ++u) l.push_back(make_int2(0, u));
+  } else {
+    int qmax = 0;
+    for (int b = 0; b < A->nblk; ++b) {
+      fill_stripe_view(A->SB[b], &d.sb[b]);
+      qmax = std::max(qmax, A->SB[b].nunits);
+    }
+    yp = static_cast<double*>(sc.get(8 * (size_t)A->nblk * A->n));
+    d.ypart = yp;
+    for (int q = 0; q < qmax; ++q)
+      for (int b = 0; b < kMaxBlk; ++b)
+        l.push_back(make_int2(0, (b < A->nblk && q < A->SB[b].nunits) ? ((b << 24) | q) : -1));
+  }
+  Desc* dd = static_cast<Desc*>(sc.get(sizeof(Desc)));
+  int2* dl = static_cast<int2*>(sc.get(sizeof(int2) * std::max<size_t>(1, l.size())));
+  PLSS_HIP(hipMemcpyAsync(dd, &d, sizeof(Desc), hipMemcpyHostToDevice, s));
+  PLSS_HIP(hipMemcpyAsync(dl, l.data(), sizeof(int2) * l.size(), hipMemcpyHostToDevice, s));
+  launch_sspmv(MODE_PLAIN, A->f32, dd, dl, (int)l.size(), transpose ? 1 : 0, s);
+  if (transpose) st_ysum(yp, A->nblk, (int)A->n, dy, s);
+  PLSS_HIP(hipStreamSynchronize(s));  // the host list goes out of scope
+}
+
 void spmv_plain(const plss_matrix* A, bool transpose, const double* x, double* y, hipStream_t s) {
   Scratch sc;
   const size_t nin = transpose ? A->m : A->n, nout = transpose ? A->n : A->m;
   double* dx = static_cast<double*>(sc.get(8 * nin));
   double* dy = static_cast<double*>(sc.get(8 * nout));
+  if (transpose ? A->t_striped : A->a_striped) {
+    PLSS_HIP(hipMemcpyAsync(dx, x, 8 * nin, hipMemcpyDefault, s));
+    stripe_plain(A, transpose, dx, dy, sc, s);
+    PLSS_HIP(hipMemcpyAsync(y, dy, 8 * nout, hipMemcpyDefault, s));
+    PLSS_HIP(hipStreamSynchronize(s));
+    return;
+  }
   Desc* dd = static_cast<Desc*>(sc.get(sizeof(Desc)));
   const PlssDir& dir = transpose ? A->T : A->A;
   int2* dl = static_cast<int2*>(sc.get(sizeof(int2) * std::max(1, dir.ntiles)));

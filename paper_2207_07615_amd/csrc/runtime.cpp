@@ -89,7 +89,171 @@ void set_tiles(PlssDir& d, int V, hipStream_t s) {
 
 size_t matrix_footprint(long long m, long long n, long long nnz, bool f32) {
   const size_t v = f32 ? 4 : 8;
-  return (size_t)nnz * (v + 4) * 2 + (size_t)(m + n + 2) * 4 + (size_t)(m + n) / 64 * 4 + 4096;
+  const bool blocked = (size_t)m * v > (3u << 20) && nnz >= 8 * 64;
+  bool as = false, ts = false;
+  auto_layout(m, n, nnz, f32, &as, &ts);
+  const int copies = 2 + (blocked ? 1 : 0) + (as ? 1 : 0) + (ts ? 1 : 0);
+  return (size_t)nnz * (v + 4) * copies + (size_t)(m + n + 2) * 4 + (size_t)(m + n) / 64 * 4 +
+         (blocked ? (size_t)kMaxBlk * (n + 1) * 4 : 0) + ((as || ts) ? (size_t)(m + n) / 64 * 4 + (1u << 20) : 0) +
+         4096;
+}
+
+// ------------------------------------------------------------------ striped layout
+
+int auto_unit_rows(long long rows, int nblk) {
+  // units per block: enough for the 256 CUs over all blocks, rounded so that
+  // every XCD gets the same count, and at most kRBmax rows each
+  const long long per_round = (256 + nblk - 1) / nblk;
+  long long nu = (rows + kRBmax - 1) / kRBmax;
+  nu = (nu + per_round - 1) / per_round * per_round;
+  long long R = (rows + nu - 1) / nu;
+  R = std::max<long long>(R, std::min<long long>(rows, 512));
+  return (int)std::max<long long>(1, std::min<long long>(R, kRBmax));
+}
+
+// Stripes pay when the gathered vector is re-read less than the entries are
+// streamed: every unit reads its whole slice of the vector once.
+void auto_layout(long long m, long long n, long long nnz, bool f32, bool* a_stripes, bool* t_stripes) {
+  *a_stripes = *t_stripes = false;
+  const double vb = f32 ? 4.0 : 8.0;
+  if (nnz < (1LL << 23)) return;
+  const double entry_bytes = (double)nnz * (4.0 + vb);
+  {
+    const int R = auto_unit_rows(m, 1);
+    const long long nu = (m + R - 1) / R;
+    const long long S = (n + kSW - 1) / kSW;
+    if (S <= kMaxStripes && nu >= 128 && (double)nu * (double)n * vb <= 0.75 * entry_bytes) *a_stripes = true;
+  }
+  if ((double)m * vb > (double)(3u << 20)) {
+    const int R = auto_unit_rows(n, kMaxBlk);
+    const long long nu = (long long)kMaxBlk * ((n + R - 1) / R);
+    const long long S = (m / kMaxBlk + kSW) / kSW;
+    if (S <= kMaxStripes && nu >= 128 && (double)nu * ((double)m / kMaxBlk) * vb <= entry_bytes) *t_stripes = true;
+  }
+}
+
+static void free_stripes(PlssStripes& st) {
+  dfree(st.pk);
+  dfree(st.val);
+  dfree(st.urow);
+  dfree(st.seg);
+  dfree(st.wsp);
+  st = PlssStripes();
+}
+
+void fill_stripe_view(const PlssStripes& st, StripeView* v) {
+  v->pk = st.pk;
+  v->val = st.val;
+  v->urow = st.urow;
+  v->seg = st.seg;
+  v->wsp = st.wsp;
+  v->nunits = st.nunits;
+  v->S = st.S;
+  v->colbase = st.colbase;
+  v->ncols = st.ncols;
+}
+
+// Striped copy of the CSR direction `src` restricted to columns
+// [colbase, colbase + ncols) (all of its entries lie there).
+static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, bool f32, PlssStripes& out,
+                          hipStream_t s) {
+  const int rows = src.nrows;
+  const long long nnz = src.h_ptr[rows];
+  const int nunits = (rows + R - 1) / R;
+  const int S = (ncols + kSW - 1) / kSW;
+  if (S > kMaxStripes) throw InvalidArg{"too many columns for the striped layout"};
+  const long long nseg = (long long)nunits * S;
+  if (nseg * 16 >= (1LL << 31) - 1) throw InvalidArg{"too many stripe segments: raise unit_rows"};
+  const size_t vb = f32 ? 4 : 8;
+  PlssStripes st;
+  int* cnt = nullptr;
+  void* work = nullptr;
+  try {
+    std::vector<int> urow(nunits + 1);
+    for (int u = 0; u <= nunits; ++u) urow[u] = (int)std::min<long long>(rows, (long long)u * R);
+    st.urow = static_cast<int*>(dmalloc(sizeof(int) * urow.size()));
+    st.seg = static_cast<int*>(dmalloc(sizeof(int) * (size_t)(nseg + 1)));
+    st.wsp = static_cast<int*>(dmalloc(sizeof(int) * (size_t)std::max<long long>(nseg * 16, 1)));
+    st.pk = static_cast<unsigned*>(dmalloc(sizeof(unsigned) * (size_t)std::max<long long>(nnz, 1)));
+    st.val = dmalloc(vb * (size_t)std::max<long long>(nnz, 1));
+    cnt = static_cast<int*>(dmalloc(sizeof(int) * (size_t)std::max<long long>(nseg, 1)));
+    work = dmalloc(sizeof(long long) * (size_t)((nseg + 1023) / 1024 + 2));
+    PLSS_HIP(hipMemcpyAsync(st.urow, urow.data(), sizeof(int) * urow.size(), hipMemcpyHostToDevice, s));
+    st_count(src.ptr, src.idx, nunits, st.urow, S, colbase, cnt, s);
+    scan_counts(cnt, (int)nseg, st.seg, work, s);
+    int total = 0;
+    PLSS_HIP(hipMemcpyAsync(&total, st.seg + nseg, sizeof(int), hipMemcpyDeviceToHost, s));
+    PLSS_HIP(hipStreamSynchronize(s));
+    if (total != nnz) {
+      set_error("striped store: entry count mismatch");
+      throw DeviceError();
+    }
+    st_scatter(src.ptr, src.idx, src.val, f32, nunits, st.urow, st.seg, S, colbase, st.pk, st.val, s);
+    st_split(st.pk, st.seg, nseg, st.wsp, s);
+    PLSS_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    dfree(cnt);
+    dfree(work);
+    free_stripes(st);
+    throw;
+  }
+  dfree(cnt);
+  dfree(work);
+  st.nunits = nunits;
+  st.S = S;
+  st.colbase = colbase;
+  st.ncols = ncols;
+  st.unit_rows = R;
+  st.nnz = nnz;
+  st.bytes = (size_t)nnz * (4 + vb) + sizeof(int) * (size_t)(nunits + 1 + (nseg + 1) + nseg * 16);
+  free_stripes(out);
+  out = st;
+}
+
+static void recount_bytes(plss_matrix* M) {
+  const size_t vsz = M->f32 ? 4 : 8;
+  const long long m = M->m, n = M->n, nnz = M->nnz;
+  size_t b = (size_t)nnz * (vsz + 4) * (M->nblk > 1 ? 3 : 2) + sizeof(int) * (size_t)(m + n + 2) +
+             sizeof(int) * (size_t)(M->A.ntiles + M->T.ntiles + 2) +
+             (M->nblk > 1 ? sizeof(int) * (size_t)M->nblk * (n + 1) : 0);
+  b += M->SA.bytes;
+  for (int q = 0; q < kMaxBlk; ++q) b += M->SB[q].bytes;
+  M->bytes = b;
+}
+
+void matrix_set_layout(plss_matrix* M, bool a_stripes, bool t_stripes, int unit_rows, hipStream_t s) {
+  if (unit_rows < 0 || unit_rows > kRBmax) throw InvalidArg{"unit_rows must be in [0, 8192]"};
+  try {
+    if (a_stripes) {
+      const int R = unit_rows ? unit_rows : auto_unit_rows(M->m, 1);
+      if (!M->a_striped || M->SA.unit_rows != R) {
+        M->a_striped = false;
+        build_stripes(M->A, 0, (int)M->n, R, M->f32, M->SA, s);
+      }
+    } else {
+      free_stripes(M->SA);
+    }
+    M->a_striped = a_stripes;
+    if (t_stripes) {
+      build_row_blocks(M, s, true);
+      const int R = unit_rows ? unit_rows : auto_unit_rows(M->n, M->nblk);
+      if (!M->t_striped || M->SB[0].unit_rows != R) {
+        M->t_striped = false;
+        for (int b = 0; b < M->nblk; ++b)
+          build_stripes(M->TB[b], M->rb[b], M->rb[b + 1] - M->rb[b], R, M->f32, M->SB[b], s);
+      }
+    } else {
+      for (int b = 0; b < kMaxBlk; ++b) free_stripes(M->SB[b]);
+    }
+    M->t_striped = t_stripes;
+  } catch (...) {
+    if (!M->a_striped) free_stripes(M->SA);
+    if (!M->t_striped)
+      for (int b = 0; b < kMaxBlk; ++b) free_stripes(M->SB[b]);
+    recount_bytes(M);
+    throw;
+  }
+  recount_bytes(M);
 }
 
 static void check_args(const plss_csr* A) {
@@ -181,10 +345,18 @@ plss_matrix* matrix_create(plss_handle* h, const plss_csr* A, plss_dtype storage
   dfree(d_rp64);
   dfree(dflag);
   dfree(work);
+  recount_bytes(M);
+  bool as = false, ts = false;
+  auto_layout(m, n, nnz, M->f32, &as, &ts);
+  if (as || ts) {
+    try {
+      matrix_set_layout(M, as, ts, 0, s);
+    } catch (...) {
+      matrix_destroy(M);
+      throw;
+    }
+  }
   h->refs += 1;
-  M->bytes = (size_t)nnz * (vsz + 4) * (M->nblk > 1 ? 3 : 2) + sizeof(int) * (size_t)(m + n + 2) +
-             sizeof(int) * (size_t)(M->A.ntiles + M->T.ntiles + 2) +
-             (M->nblk > 1 ? sizeof(int) * (size_t)M->nblk * (n + 1) : 0);
   return M;
 }
 
@@ -203,7 +375,9 @@ void matrix_destroy(plss_matrix* M) {
     dfree(d.val);
     dfree(d.tile);
     dfree(d.grp);
+    free_stripes(M->SB[b]);
   }
+  free_stripes(M->SA);
   dfree(M->tb_ptr_all);
   delete M;
 }
@@ -213,10 +387,11 @@ void matrix_destroy(plss_matrix* M) {
 // splitting the rows into 8 blocks of equal nnz gives every XCD a slice of
 // r that does.  Block b holds, column by column, the entries of its rows
 // (a contiguous sub-segment of each CSC column).
-void build_row_blocks(plss_matrix* M, hipStream_t s) {
+void build_row_blocks(plss_matrix* M, hipStream_t s, bool force) {
   const size_t vb = M->f32 ? 4 : 8;
   const long long m = M->m, n = M->n, nnz = M->nnz;
-  if ((size_t)m * vb <= (3u << 20) || nnz < 8 * 64) {
+  if (M->nblk > 1) return;
+  if (!force && ((size_t)m * vb <= (3u << 20) || nnz < 8 * 64)) {
     M->nblk = 1;
     return;
   }

@@ -23,6 +23,19 @@ struct PlssDir {
   std::vector<int> h_ptr;  // host copy of ptr (tile construction)
 };
 
+// A striped store of one direction (stripe.hip): units of unit_rows rows,
+// stripes of kSW columns of the gathered vector.
+struct PlssStripes {
+  unsigned* pk = nullptr;  // nnz packed (row in unit, column in stripe)
+  void* val = nullptr;     // nnz values (storage precision)
+  int* urow = nullptr;     // nunits + 1
+  int* seg = nullptr;      // nunits * S + 1
+  int* wsp = nullptr;      // nunits * S * 16
+  int nunits = 0, S = 0, colbase = 0, ncols = 0, unit_rows = 0;
+  long long nnz = 0;
+  size_t bytes = 0;
+};
+
 struct plss_handle {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -46,6 +59,11 @@ struct plss_matrix {
   int rb[plss::kMaxBlk + 1] = {0};
   PlssDir TB[plss::kMaxBlk];
   int* tb_ptr_all = nullptr;   // nblk x (n+1) pointers shared by the blocks
+  // striped stores: SA for products with A, SB[b] for row block b of Aᵀ
+  bool a_striped = false, t_striped = false;
+  PlssStripes SA;
+  PlssStripes SB[plss::kMaxBlk];
+  size_t base_bytes = 0;       // bytes of the CSR, CSC and row-blocked stores
   size_t bytes = 0;
 };
 
@@ -64,7 +82,14 @@ void set_tiles(PlssDir& d, int V, hipStream_t s);
 plss_matrix* matrix_create(plss_handle* h, const plss_csr* A, plss_dtype storage, hipStream_t s);
 void matrix_destroy(plss_matrix* A);
 void handle_release(plss_handle* h);  // drop one reference; frees a closed handle at zero
-void build_row_blocks(plss_matrix* M, hipStream_t s);
+void build_row_blocks(plss_matrix* M, hipStream_t s, bool force = false);
 size_t matrix_footprint(long long m, long long n, long long nnz, bool f32);
+
+// Striped layout: build or drop the stores (unit_rows 0 = from the shape).
+void matrix_set_layout(plss_matrix* M, bool a_stripes, bool t_stripes, int unit_rows, hipStream_t s);
+// Layout chosen from the shape at creation.
+void auto_layout(long long m, long long n, long long nnz, bool f32, bool* a_stripes, bool* t_stripes);
+int auto_unit_rows(long long rows, int nblk);
+void fill_stripe_view(const PlssStripes& st, StripeView* v);
 
 }  // namespace plss

@@ -43,6 +43,7 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
   char* d_lists = nullptr;
   State* h_state = nullptr;
   try {
+    run.use_stripes = false;  // the one-column steps use the tile partition of the partials
     run.setup(A, b, o, std::min<long long>(o->maxit + 2, 1LL << 22), d_state, nullptr);
     run.upload(b, nullptr, nullptr, s);
     const int wblk = (m + 1023) / 1024;

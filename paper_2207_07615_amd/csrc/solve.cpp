@@ -49,7 +49,9 @@ void SysRun::setup(const plss_matrix* M, const double* b_in, const plss_opts* o,
   const size_t o_b = take(8 * m), o_xo = take(8 * n), o_x = f32 ? take(8 * n) : 0, o_r64 = take(8 * m);
   const size_t o_r = take(vs * m), o_p = take(vs * n), o_y = take(vs * n), o_c = f32 ? take(vs * m) : 0;
   const size_t o_wi = o->wi_diag ? take(8 * n) : 0;
-  const size_t o_pr = take(8 * M->A.ntiles), o_pb = take(8 * M->A.ntiles);
+  const bool as = use_stripes && M->a_striped, ts = use_stripes && M->t_striped;
+  const int rho_cnt = as ? M->SA.nunits : M->A.ntiles;
+  const size_t o_pr = take(8 * (size_t)rho_cnt), o_pb = take(8 * (size_t)rho_cnt);
   const size_t o_pp = take(8 * (size_t)std::max(M->T.ntiles, u_nblk)), o_pt = take(8 * u_nblk);
   const size_t o_yp = M->nblk > 1 ? take(vs * n * M->nblk) : 0;
   const size_t o_h = take(8 * (size_t)hist_len);
@@ -81,6 +83,12 @@ void SysRun::setup(const plss_matrix* M, const double* b_in, const plss_opts* o,
     desc.tb_tile[b] = M->TB[b].tile;
     desc.tb_grp[b] = M->TB[b].grp;
   }
+  desc.a_striped = as ? 1 : 0;
+  desc.t_striped = ts ? 1 : 0;
+  desc.rho_cnt = rho_cnt;
+  if (as) fill_stripe_view(M->SA, &desc.sa);
+  if (ts)
+    for (int b = 0; b < M->nblk; ++b) fill_stripe_view(M->SB[b], &desc.sb[b]);
   desc.ypart = M->nblk > 1 ? arena + o_yp : nullptr;
   desc.phi_cnt = M->nblk > 1 ? u_nblk : M->T.ntiles;
   desc.b = reinterpret_cast<double*>(arena + o_b);
@@ -142,7 +150,7 @@ ListSet::~ListSet() {
 }
 
 void ListSet::build(const std::vector<std::pair<int, const SysRun*>>& items, hipStream_t s) {
-  std::map<int, std::vector<int2>> la, lt, lu, laf;
+  std::map<int, std::vector<int2>> la, lt, lu, laf, lsa, lsb;
   std::vector<int> ls;
   any_f32 = any_blk = false;
   for (const auto& it : items) {
@@ -151,13 +159,30 @@ void ListSet::build(const std::vector<std::pair<int, const SysRun*>>& items, hip
     const plss_matrix* M = r.A;
     const int f = r.f32 ? 1 : 0;
     any_f32 |= r.f32;
-    auto& A = la[f * 100 + M->A.V];
     auto& AF = laf[f];
-    for (int t = 0; t < M->A.ntiles; ++t) {
-      A.push_back(make_int2(i, t));
-      AF.push_back(make_int2(i, t));
+    if (r.desc.a_striped) {
+      auto& A = lsa[f];
+      for (int q = 0; q < M->SA.nunits; ++q) {
+        A.push_back(make_int2(i, q));
+        AF.push_back(make_int2(i, q));
+      }
+    } else {
+      auto& A = la[f * 100 + M->A.V];
+      for (int t = 0; t < M->A.ntiles; ++t) {
+        A.push_back(make_int2(i, t));
+        AF.push_back(make_int2(i, t));
+      }
     }
-    if (M->nblk > 1) {
+    if (r.desc.t_striped) {
+      // unit q of block b at position 8 q + b: block b's units run on XCD b
+      any_blk = true;
+      auto& T = lsb[f];
+      int qmax = 0;
+      for (int b = 0; b < M->nblk; ++b) qmax = std::max(qmax, M->SB[b].nunits);
+      for (int q = 0; q < qmax; ++q)
+        for (int b = 0; b < kMaxBlk; ++b)
+          T.push_back(make_int2(i, (b < M->nblk && q < M->SB[b].nunits) ? ((b << 24) | q) : -1));
+    } else if (M->nblk > 1) {
       any_blk = true;
       auto& T = lt[1000 + f * 100 + M->T.V];
       int qmax = 0;
@@ -174,7 +199,7 @@ void ListSet::build(const std::vector<std::pair<int, const SysRun*>>& items, hip
     ls.push_back(i);
   }
   size_t total = ls.size() * sizeof(int) + 64;
-  for (auto* mp : {&la, &lt, &lu, &laf})
+  for (auto* mp : {&la, &lt, &lu, &laf, &lsa, &lsb})
     for (auto& kv : *mp) total += kv.second.size() * sizeof(int2) + 64;
   if (total > cap) {
     dfree(d);
@@ -201,6 +226,8 @@ void ListSet::build(const std::vector<std::pair<int, const SysRun*>>& items, hip
   put(lt, t);
   put(lu, u);
   put(laf, af);
+  put(lsa, sa);
+  put(lsb, sb);
   std::memcpy(hbuf + off, ls.data(), ls.size() * sizeof(int));
   sys = reinterpret_cast<const int*>(d + off);
   nsys = (int)ls.size();
@@ -211,6 +238,7 @@ void ListSet::build(const std::vector<std::pair<int, const SysRun*>>& items, hip
 void ListSet::outer_seq(const Desc* dd, hipStream_t s) const {
   for (auto& g : u) launch_axpy_out(dd, g.list, g.n, s);
   for (auto& g : a) launch_spmv(MODE_REFINE, g.key >= 100, g.key % 100, dd, g.list, g.n, 0, s);
+  for (auto& g : sa) launch_sspmv(MODE_REFINE, g.key == 1, dd, g.list, g.n, 0, s);
   launch_outer(dd, sys, nsys, s);
   for (auto& g : af) launch_start(g.key == 1, dd, g.list, g.n, s);
 }
@@ -218,11 +246,13 @@ void ListSet::outer_seq(const Desc* dd, hipStream_t s) const {
 void ListSet::iteration(const Desc* dd, hipStream_t s, hipEvent_t* ev) const {
   if (ev) PLSS_HIP(hipEventRecord(ev[0], s));
   for (auto& g : a) launch_spmv(MODE_RESID, g.key >= 100, g.key % 100, dd, g.list, g.n, 0, s);
+  for (auto& g : sa) launch_sspmv(MODE_RESID, g.key == 1, dd, g.list, g.n, 0, s);
   if (ev) PLSS_HIP(hipEventRecord(ev[1], s));
   for (auto& g : t) {
     const int k = g.key % 1000;
     launch_spmv(g.key >= 1000 ? MODE_TRANSB : MODE_TRANS, k >= 100, k % 100, dd, g.list, g.n, 1, s);
   }
+  for (auto& g : sb) launch_sspmv(MODE_TRANSB, g.key == 1, dd, g.list, g.n, 1, s);
   if (any_blk)
     for (auto& g : u) launch_ycomb(g.key == 1, dd, g.list, g.n, s);
   if (ev) PLSS_HIP(hipEventRecord(ev[2], s));

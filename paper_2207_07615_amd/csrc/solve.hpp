@@ -20,6 +20,7 @@ struct SysRun {
   size_t bytes = 0;
   long long hist_len = 0;
   int u_nblk = 0;
+  bool use_stripes = true;  // the residual path may use the matrix's striped stores
   ~SysRun();
   void setup(const plss_matrix* M, const double* b, const plss_opts* o, long long hist_len,
              State* d_state, Desc* unused);
@@ -38,6 +39,7 @@ struct ListSet {
     int n;
   };
   std::vector<Group> a, t, u, af;
+  std::vector<Group> sa, sb;  // striped units: products with A, block products with Aᵀ
   const int* sys = nullptr;
   int nsys = 0;
   bool any_f32 = false, any_blk = false;

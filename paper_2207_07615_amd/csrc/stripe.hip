@@ -1,0 +1,433 @@
+// Striped sparse products: the gathered vector passes through LDS.
+//
+// A CSR product whose gathered vector x does not stay in a CU's caches is
+// bound by the rate of scattered L2 requests, not by HBM.  The striped store
+// turns the gather into a stream: a workgroup owns a block of rows (a
+// "unit"), keeps the unit's row sums in LDS, and walks the columns in
+// stripes of kSW entries, staging each stripe's slice of x in LDS.  The
+// entries of a unit are stored stripe by stripe and, inside a stripe, in
+// CSR order (row, then column); each entry packs its row inside the unit
+// and its column inside the stripe into one 32-bit word, so it still costs
+// 4 + value bytes.
+//
+// Inside a (unit, stripe) segment the 16 waves of the workgroup take 16
+// consecutive ranges of entries whose boundaries fall on row starts (fixed
+// when the store is built), so every row's stripe sum has exactly one
+// writer.  A wave walks its range in windows of 64*Q entries (Q per lane,
+// Q <= 8 chosen from the range length); each lane sums its runs of equal
+// rows, and a wave-level segmented scan carries the open run from lane to
+// lane and from window to window.  Stripes are applied in order, so each
+// row sum has one fixed order: the product is deterministic and does not
+// depend on which other systems share the launch.
+#include "kernels.hpp"
+
+namespace plss {
+
+namespace {
+
+constexpr int kST = kSThreads;       // threads of the striped workgroups
+constexpr int kSWaves = kST / 64;    // waves per striped workgroup
+constexpr int kQmax = 8;             // entries per lane of one window
+
+template <class T>
+__device__ __forceinline__ T swsum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Exclusive segmented scan over the 64 lanes: a set flag starts a new
+// segment after the element (incl_j = f_j ? v_j : incl_{j-1} + v_j).
+template <class T>
+__device__ __forceinline__ T wseg_excl(int f, T v) {
+  const int lane = threadIdx.x & 63;
+  T sv = v;
+  int sf = f;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    T ov = __shfl_up(sv, off, 64);
+    int of = __shfl_up(sf, off, 64);
+    if (lane >= off) {
+      if (!sf) sv = ov + sv;
+      sf |= of;
+    }
+  }
+  T ex = __shfl_up(sv, 1, 64);
+  if (lane == 0) ex = T(0);
+  return ex;
+}
+
+// first index i in [lo, hi) with a[i] > key (a non-decreasing)
+__device__ __forceinline__ int upper_bound_i(const int* __restrict__ a, int lo, int hi, int key) {
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (a[mid] <= key) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ build
+
+// cnt[u * S + s] = entries of unit u whose column lies in stripe s.  The
+// source is a CSR direction whose column indices are offset by colbase.
+__global__ __launch_bounds__(kST) void k_st_count(const int* __restrict__ ptr, const int* __restrict__ idx,
+                                                  const int* __restrict__ urow, int S, int colbase,
+                                                  int* __restrict__ cnt) {
+  extern __shared__ int s_h[];
+  const int u = blockIdx.x;
+  for (int s = threadIdx.x; s < S; s += kST) s_h[s] = 0;
+  __syncthreads();
+  const int e0 = ptr[urow[u]], e1 = ptr[urow[u + 1]];
+  for (int e = e0 + threadIdx.x; e < e1; e += kST) atomicAdd(&s_h[(idx[e] - colbase) / kSW], 1);
+  __syncthreads();
+  for (int s = threadIdx.x; s < S; s += kST) cnt[(size_t)u * S + s] = s_h[s];
+}
+
+// Stable scatter of one unit's entries into stripe order.  The unit's
+// entries are taken kST at a time in CSR order; a batch is sorted in LDS by
+// the key (stripe, position in the batch) (bitonic network), which gives
+// each entry its rank among the batch's entries of the same stripe, and a
+// per-stripe cursor (starting at the segment start seg[u * S + s]) places
+// the batches one after the other.  CSR order is kept inside every stripe.
+template <class Val>
+__global__ __launch_bounds__(kST) void k_st_scatter(const int* __restrict__ ptr, const int* __restrict__ idx,
+                                                    const Val* __restrict__ val, const int* __restrict__ urow,
+                                                    const int* __restrict__ seg, int S, int colbase,
+                                                    unsigned* __restrict__ opk, Val* __restrict__ oval) {
+  extern __shared__ int s_cur[];  // S cursors
+  __shared__ unsigned s_key[kST];
+  __shared__ unsigned s_pk[kST];
+  __shared__ Val s_val[kST];
+  const int u = blockIdx.x;
+  const int r0 = urow[u], r1 = urow[u + 1];
+  for (int s = threadIdx.x; s < S; s += kST) s_cur[s] = seg[(size_t)u * S + s];
+  const int e0 = ptr[r0], e1 = ptr[r1];
+  const int t = threadIdx.x;
+  for (int base = e0; base < e1; base += kST) {
+    const int e = base + t;
+    unsigned key = 0xFFFFFFFFu;
+    if (e < e1) {
+      const int col = idx[e] - colbase;
+      const int st = col / kSW;
+      const int row = upper_bound_i(ptr, r0, r1 + 1, e) - 1;  // ptr[row] <= e < ptr[row + 1]
+      s_pk[t] = ((unsigned)(row - r0) << 16) | (unsigned)(col - st * kSW);
+      s_val[t] = val[e];
+      key = ((unsigned)st << 10) | (unsigned)t;
+    }
+    s_key[t] = key;
+    __syncthreads();
+    for (int k = 2; k <= kST; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const int p = t ^ j;
+        if (p > t) {
+          const unsigned a = s_key[t], b = s_key[p];
+          const bool up = (t & k) == 0;
+          if ((a > b) == up) {
+            s_key[t] = b;
+            s_key[p] = a;
+          }
+        }
+        __syncthreads();
+      }
+    }
+    // thread t now handles sorted position t
+    const unsigned k0 = s_key[t];
+    int st = -1, first = 0;
+    bool last = false;
+    if (k0 != 0xFFFFFFFFu) {
+      st = (int)(k0 >> 10);
+      const unsigned lo_key = (unsigned)st << 10;
+      int lo = 0, hi = t;  // first position with key >= lo_key
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_key[mid] < lo_key) lo = mid + 1;
+        else hi = mid;
+      }
+      first = lo;
+      const int src = (int)(k0 & 1023u);
+      const int dst = s_cur[st] + (t - first);
+      opk[dst] = s_pk[src];
+      oval[dst] = s_val[src];
+      last = (t + 1 == kST) || (int)(s_key[t + 1] >> 10) != st;
+    }
+    __syncthreads();
+    if (last) s_cur[st] += t + 1 - first;
+    __syncthreads();
+  }
+}
+
+// Row-aligned wave ranges of every segment: wave w starts at the first row
+// start at or after segment start + len * w / 16.
+__global__ void k_st_split(const unsigned* __restrict__ pk, const int* __restrict__ seg, long long nseg,
+                           int* __restrict__ wsp) {
+  const long long total = nseg * kSWaves;
+  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < total;
+       q += (long long)gridDim.x * blockDim.x) {
+    const long long g = q / kSWaves;
+    const int w = (int)(q % kSWaves);
+    const int b0 = seg[g], b1 = seg[g + 1];
+    int t = b0 + (int)((long long)(b1 - b0) * w / kSWaves);
+    while (t > b0 && t < b1 && (pk[t] >> 16) == (pk[t - 1] >> 16)) ++t;
+    wsp[q] = t;
+  }
+}
+
+// ------------------------------------------------------------------ product
+
+// One workgroup per (system, unit).  MODE_RESID: r <- r - A p, partial rho
+// per unit.  MODE_TRANSB: ypart[b] <- A_bᵀ r_b for row block b of A (the
+// unit list entry carries b << 24 | unit).  MODE_REFINE: r64 <- b - A x in
+// float64, partials of ||r64||^2 and ||b||^2.  MODE_PLAIN: r64 <- A p
+// (float64), or ypart[b] <- A_bᵀ p for a transposed store; no state.
+template <class Val, class Vin, class Acc, int MODE>
+__global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const int2* __restrict__ list,
+                                               int transposed) {
+  __shared__ Acc s_x[2][kSW];
+  __shared__ Acc s_acc[kRBmax];
+  __shared__ double s_red[2][kSWaves];
+
+  const int2 ent = list[blockIdx.x];
+  if (ent.y < 0) return;  // padding of an XCD-interleaved list
+  const Desc* d = D + ent.x;
+  if (MODE != MODE_PLAIN) {
+    const State* st = d->st;
+    if (MODE == MODE_REFINE) {
+      if (st->final_done || !st->done) return;
+    } else {
+      if (st->final_done || st->done) return;
+      if (MODE == MODE_RESID && st->k == 0) return;
+    }
+  }
+  const bool tb = MODE == MODE_TRANSB || (MODE == MODE_PLAIN && transposed);
+  const int blk = tb ? (ent.y >> 24) : 0;
+  const int u = tb ? (ent.y & 0xFFFFFF) : ent.y;
+  const StripeView& sv = tb ? d->sb[blk] : d->sa;
+  const unsigned* __restrict__ pk = sv.pk;
+  const Val* __restrict__ val = static_cast<const Val*>(sv.val);
+  const int S = sv.S;
+  const int r0 = sv.urow[u], nr = sv.urow[u + 1] - r0;
+  const Vin* __restrict__ x;
+  int xlen;
+  if (MODE == MODE_RESID || (MODE == MODE_PLAIN && !tb)) {
+    x = static_cast<const Vin*>(d->p);
+    xlen = d->n;
+  } else if (MODE == MODE_REFINE) {
+    x = reinterpret_cast<const Vin*>(d->xo);
+    xlen = d->n;
+  } else if (MODE == MODE_TRANSB) {
+    x = static_cast<const Vin*>(d->r) + sv.colbase;
+    xlen = sv.ncols;
+  } else {
+    x = static_cast<const Vin*>(d->p) + sv.colbase;
+    xlen = sv.ncols;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+
+  for (int i = threadIdx.x; i < nr; i += kST) s_acc[i] = Acc(0);
+  for (int j = threadIdx.x; j < kSW; j += kST) s_x[0][j] = j < xlen ? Acc(x[j]) : Acc(0);
+  __syncthreads();
+
+  const int* __restrict__ seg = sv.seg + (size_t)u * S;
+  const int* __restrict__ wsp = sv.wsp + (size_t)u * S * kSWaves;
+  for (int s = 0; s < S; ++s) {
+    // the next stripe's slice of x travels in registers during this stripe
+    Acc nx[kSW / kST];
+#pragma unroll
+    for (int q = 0; q < kSW / kST; ++q) {
+      const int j = (s + 1) * kSW + q * kST + threadIdx.x;
+      nx[q] = (s + 1 < S && j < xlen) ? Acc(x[j]) : Acc(0);
+    }
+    const Acc* __restrict__ xs = s_x[s & 1];
+    const int ws = wsp[s * kSWaves + w];
+    const int we = (w + 1 < kSWaves) ? wsp[s * kSWaves + w + 1] : seg[s + 1];
+    const int len = we - ws;
+    if (len > 0) {
+      int Q = (len + 63) >> 6;
+      if (Q > kQmax) Q = kQmax;
+      Acc wc = Acc(0);  // open row sum carried from the previous window
+      for (int base = ws; base < we; base += 64 * Q) {
+        const int wend = min(base + 64 * Q, we);
+        const int q0 = base + lane * Q;
+        unsigned pv[kQmax];
+        Val vv[kQmax];
+#pragma unroll
+        for (int q = 0; q < kQmax; ++q) {
+          if (q < Q && q0 + q < wend) {
+            pv[q] = __builtin_nontemporal_load(&pk[q0 + q]);
+            vv[q] = __builtin_nontemporal_load(&val[q0 + q]);
+          } else {
+            pv[q] = 0xFFFFFFFFu;
+            vv[q] = Val(0);
+          }
+        }
+        // row of the entry after this lane's last one (-1: the range ends)
+        const int frow = q0 < wend ? (int)(pv[0] >> 16) : -1;
+        const int nb = __shfl_down(frow, 1, 64);
+        int nrow = -1;
+        if (q0 + Q < wend) nrow = nb;
+        else if (q0 + Q == wend && wend < we) nrow = (int)(__builtin_nontemporal_load(&pk[wend]) >> 16);
+        int cur = -1, fr = 0;
+        bool hend = false;
+        Acc acc = Acc(0), fv = Acc(0);
+#pragma unroll
+        for (int q = 0; q < kQmax; ++q) {
+          if (q < Q && q0 + q < wend) {
+            const int r = (int)(pv[q] >> 16);
+            const Acc prod = Acc(vv[q]) * xs[pv[q] & 0xFFFFu];
+            if (r != cur) {
+              if (cur >= 0) {
+                if (!hend) {
+                  hend = true;
+                  fr = cur;
+                  fv = acc;
+                } else {
+                  s_acc[cur] += acc;
+                }
+              }
+              acc = Acc(0);
+              cur = r;
+            }
+            acc += prod;
+          }
+        }
+        if (cur >= 0 && nrow != cur) {
+          if (!hend) {
+            hend = true;
+            fr = cur;
+            fv = acc;
+          } else {
+            s_acc[cur] += acc;
+          }
+          acc = Acc(0);
+        }
+        if (lane == 0) {
+          if (hend) fv = wc + fv;
+          else acc = wc + acc;
+        }
+        const Acc carry = wseg_excl<Acc>(hend ? 1 : 0, acc);
+        if (hend) s_acc[fr] += fv + carry;
+        const Acc incl = hend ? acc : carry + acc;
+        wc = __shfl(incl, 63, 64);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kSW / kST; ++q) s_x[(s + 1) & 1][q * kST + threadIdx.x] = nx[q];
+    __syncthreads();
+  }
+
+  // epilogue over the unit's rows
+  double part = 0.0, part2 = 0.0;
+  for (int i = threadIdx.x; i < nr; i += kST) {
+    const int row = r0 + i;
+    const Acc sum = s_acc[i];
+    if (MODE == MODE_RESID) {
+      Vin* r = static_cast<Vin*>(d->r);
+      const Acc rn = Acc(r[row]) - sum;
+      r[row] = Vin(rn);
+      part += double(rn) * double(rn);
+    } else if (MODE == MODE_TRANSB) {
+      static_cast<Vin*>(d->ypart)[(size_t)blk * d->n + row] = Vin(sum);
+    } else if (MODE == MODE_REFINE) {
+      const double bi = d->b[row];
+      const double ri = bi - double(sum);
+      d->r64[row] = ri;
+      part += ri * ri;
+      part2 += bi * bi;
+    } else if (tb) {
+      static_cast<double*>(d->ypart)[(size_t)blk * d->n + row] = double(sum);
+    } else {
+      d->r64[row] = double(sum);
+    }
+  }
+  if (MODE == MODE_TRANSB || MODE == MODE_PLAIN) return;
+  part = swsum(part);
+  part2 = swsum(part2);
+  if (lane == 0) {
+    s_red[0][w] = part;
+    s_red[1][w] = part2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = s_red[0][0], b2 = s_red[1][0];
+    for (int q = 1; q < kSWaves; ++q) {
+      a += s_red[0][q];
+      b2 += s_red[1][q];
+    }
+    d->part_rho[u] = a;
+    if (MODE == MODE_REFINE) d->part_b[u] = b2;
+  }
+}
+
+// y_j = sum over row blocks of ypart[b][j] in block order (plain products)
+__global__ void k_st_ysum(const double* __restrict__ yp, int nblk, int n, double* __restrict__ y) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    double s = yp[j];
+    for (int b = 1; b < nblk; ++b) s += yp[(size_t)b * n + j];
+    y[j] = s;
+  }
+}
+
+// ------------------------------------------------------------------ host side
+
+static int st_grid(long long work, int per_block) {
+  long long g = (work + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > 65536) g = 65536;
+  return (int)g;
+}
+
+void st_count(const int* ptr, const int* idx, int nunits, const int* d_urow, int S, int colbase, int* d_cnt,
+              hipStream_t s) {
+  if (nunits <= 0 || S <= 0) return;
+  k_st_count<<<nunits, kST, sizeof(int) * (size_t)S, s>>>(ptr, idx, d_urow, S, colbase, d_cnt);
+  PLSS_HIP(hipGetLastError());
+}
+
+void st_scatter(const int* ptr, const int* idx, const void* val, bool f32, int nunits, const int* d_urow,
+                const int* d_seg, int S, int colbase, unsigned* opk, void* oval, hipStream_t s) {
+  if (nunits <= 0 || S <= 0) return;
+  const size_t lds = sizeof(int) * (size_t)S;
+  if (f32)
+    k_st_scatter<float><<<nunits, kST, lds, s>>>(ptr, idx, static_cast<const float*>(val), d_urow, d_seg, S,
+                                                 colbase, opk, static_cast<float*>(oval));
+  else
+    k_st_scatter<double><<<nunits, kST, lds, s>>>(ptr, idx, static_cast<const double*>(val), d_urow, d_seg, S,
+                                                  colbase, opk, static_cast<double*>(oval));
+  PLSS_HIP(hipGetLastError());
+}
+
+void st_split(const unsigned* pk, const int* d_seg, long long nseg, int* d_wsp, hipStream_t s) {
+  if (nseg <= 0) return;
+  k_st_split<<<st_grid(nseg * kSWaves, 256), 256, 0, s>>>(pk, d_seg, nseg, d_wsp);
+  PLSS_HIP(hipGetLastError());
+}
+
+void st_ysum(const double* ypart, int nblk, int n, double* y, hipStream_t s) {
+  k_st_ysum<<<st_grid(n, 256), 256, 0, s>>>(ypart, nblk, n, y);
+  PLSS_HIP(hipGetLastError());
+}
+
+void launch_sspmv(int mode, bool f32, const Desc* d, const int2* list, int n, int transposed, hipStream_t s) {
+  if (n <= 0) return;
+  if (!f32) {
+    switch (mode) {
+      case MODE_RESID: k_sspmv<double, double, double, MODE_RESID><<<n, kST, 0, s>>>(d, list, 0); break;
+      case MODE_TRANSB: k_sspmv<double, double, double, MODE_TRANSB><<<n, kST, 0, s>>>(d, list, 1); break;
+      case MODE_REFINE: k_sspmv<double, double, double, MODE_REFINE><<<n, kST, 0, s>>>(d, list, 0); break;
+      default: k_sspmv<double, double, double, MODE_PLAIN><<<n, kST, 0, s>>>(d, list, transposed); break;
+    }
+  } else {
+    switch (mode) {
+      case MODE_RESID: k_sspmv<float, float, float, MODE_RESID><<<n, kST, 0, s>>>(d, list, 0); break;
+      case MODE_TRANSB: k_sspmv<float, float, float, MODE_TRANSB><<<n, kST, 0, s>>>(d, list, 1); break;
+      case MODE_REFINE: k_sspmv<float, double, double, MODE_REFINE><<<n, kST, 0, s>>>(d, list, 0); break;
+      default: k_sspmv<float, double, double, MODE_PLAIN><<<n, kST, 0, s>>>(d, list, transposed); break;
+    }
+  }
+  PLSS_HIP(hipGetLastError());
+}
+
+}  // namespace plss

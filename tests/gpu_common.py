@@ -50,7 +50,7 @@ def order_spread(A, b, k, wi=None, x0=None):
     return ref, spread
 
 
-def fp64_parity(h, sysm, tol=1e-8, maxit=5000, wi=None, storage="f64"):
+def fp64_parity(h, sysm, tol=1e-8, maxit=5000, wi=None, storage="f64", layout=None):
     """Check a float64 solve against Algorithm 1 (oracle):
 
     * the GPU meets the stop test and its iteration count is within one of
@@ -66,6 +66,8 @@ def fp64_parity(h, sysm, tol=1e-8, maxit=5000, wi=None, storage="f64"):
     import paper_2207_07615_amd as plss
     from oracle import plss as O
     M = matrix(h, sysm.A, storage)
+    if layout is not None:
+        M.layout(**layout)
     x, info, hist = plss.solve(h, M, sysm.b, tol=tol, maxit=maxit, wi=wi)
     assert info["status"] == 0, info
     k = info["iters"]
