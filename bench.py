@@ -361,6 +361,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 + refinement arm")
     ap.add_argument("--autotune", action="store_true", help="pick tile widths by measurement")
+    ap.add_argument("--layout", default="auto", choices=["auto", "tiles", "stripes"],
+                    help="product layout of the large workload (auto: chosen from the shape)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a 1 GiB device copy (calibrates profiler byte counters)")
     ap.add_argument("--config", default="large",
@@ -399,6 +401,11 @@ def main():
     log(f"device store (upload + CSC) in {time.perf_counter() - t0:.2f}s")
     if args.autotune:
         log(f"tile widths {M.autotune()}")
+    if args.layout != "auto":
+        on = args.layout == "stripes"
+        M.layout(a_stripes=on, t_stripes=on)
+    layout = M.layout()
+    log(f"layout {layout}")
     b = torch.from_numpy(sysm.b).to(dev)
     torch.cuda.synchronize()
 
@@ -455,7 +462,8 @@ def main():
         "data": "synthetic (seeded; stands in for the paper's SuiteSparse matrices)",
         "config": {"workload": "large: 2,000,000 x 500,000 CSR, Zipf(1.5) rows clipped to [2,2000], "
                                "N(0,1), residual sketch, FP64, rel. tol 1e-8",
-                   "m": A.m, "n": A.n, "nnz": A.nnz, "tol": 1e-8, "maxit": 1000},
+                   "m": A.m, "n": A.n, "nnz": A.nnz, "tol": 1e-8, "maxit": 1000,
+                   "layout": layout},
         "iters_per_solve": tot_iters / args.steps,
         "solves_per_s": args.steps / wall,
         "p50_ms": lat_ms[len(lat_ms) // 2],
@@ -477,6 +485,9 @@ def main():
         M32 = plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n), storage="f32")
         if args.autotune:
             M32.autotune()
+        if args.layout != "auto":
+            on = args.layout == "stripes"
+            M32.layout(a_stripes=on, t_stripes=on)
         kw32 = dict(tol=1e-8, maxit=4000, refine=True, inner_tol=1e-4, max_outer=20)
         plss.solve(h, M32, b32, **kw32)
         torch.cuda.synchronize()
@@ -495,6 +506,7 @@ def main():
             "speedup_vs_fp64_solves": (n32 / w32) / (args.steps / wall),
             "iters_per_s": sum(its32) / w32,
             "hbm_gbps_iteration": bytes_model(A.m, A.n, A.nnz, True)["iter"] * sum(its32) / w32 / 1e9,
+            "layout": M32.layout(),
         }
         del M32
 

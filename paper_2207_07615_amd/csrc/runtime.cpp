@@ -190,7 +190,22 @@ static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, boo
     }
     st_scatter(src.ptr, src.idx, src.val, f32, nunits, st.urow, st.seg, S, colbase, st.pk, st.val, s);
     st_split(st.pk, st.seg, nseg, st.wsp, s);
-    PLSS_HIP(hipStreamSynchronize(s));
+    // lane-interleaved windows (out of place, then the CSR-ordered copy goes)
+    unsigned* ipk = static_cast<unsigned*>(dmalloc(sizeof(unsigned) * (size_t)std::max<long long>(nnz, 1)));
+    void* ival = nullptr;
+    try {
+      ival = dmalloc(vb * (size_t)std::max<long long>(nnz, 1));
+      st_interleave(st.pk, st.val, f32, st.seg, st.wsp, nseg, ipk, ival, s);
+      PLSS_HIP(hipStreamSynchronize(s));
+    } catch (...) {
+      dfree(ipk);
+      dfree(ival);
+      throw;
+    }
+    dfree(st.pk);
+    dfree(st.val);
+    st.pk = ipk;
+    st.val = ival;
   } catch (...) {
     dfree(cnt);
     dfree(work);

@@ -5,20 +5,26 @@
 // turns the gather into a stream: a workgroup owns a block of rows (a
 // "unit"), keeps the unit's row sums in LDS, and walks the columns in
 // stripes of kSW entries, staging each stripe's slice of x in LDS.  The
-// entries of a unit are stored stripe by stripe and, inside a stripe, in
-// CSR order (row, then column); each entry packs its row inside the unit
+// entries of a unit are grouped stripe by stripe and, inside a stripe, kept
+// in CSR order (row, then column); each entry packs its row inside the unit
 // and its column inside the stripe into one 32-bit word, so it still costs
 // 4 + value bytes.
 //
 // Inside a (unit, stripe) segment the 16 waves of the workgroup take 16
 // consecutive ranges of entries whose boundaries fall on row starts (fixed
 // when the store is built), so every row's stripe sum has exactly one
-// writer.  A wave walks its range in windows of 64*Q entries (Q per lane,
-// Q <= 8 chosen from the range length); each lane sums its runs of equal
-// rows, and a wave-level segmented scan carries the open run from lane to
-// lane and from window to window.  Stripes are applied in order, so each
-// row sum has one fixed order: the product is deterministic and does not
-// depend on which other systems share the launch.
+// writer.  A wave walks its range in windows of at most 64*Q entries (Q <= 8
+// per lane, chosen from the range length): each lane takes a run of
+// consecutive entries, sums its runs of equal rows, and a wave-level
+// segmented scan (DPP row shifts and broadcasts) carries the open run from
+// lane to lane and from window to window.  Each window is stored
+// lane-interleaved (the lane's k-th entry at window start + 64 k + lane), so
+// every load instruction of the wave reads 64 consecutive entries.  Stripes
+// are applied in order, so each row sum has one fixed order: the product is
+// deterministic and does not depend on which other systems share a launch.
+// The next stripe's wave bounds are read two stripes ahead and its first
+// window one stripe ahead, so their memory latency overlaps the current
+// stripe's arithmetic.
 #include "kernels.hpp"
 
 namespace plss {
@@ -36,25 +42,75 @@ __device__ __forceinline__ T swsum(T v) {
   return v;
 }
 
-// Exclusive segmented scan over the 64 lanes: a set flag starts a new
-// segment after the element (incl_j = f_j ? v_j : incl_{j-1} + v_j).
+// DPP controls of GFX9-family wave64 cross-lane moves
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kWaveShl1 = 0x130, kWaveShr1 = 0x138;
+
+// v from another lane per the DPP control; lanes without a source (or outside
+// row_mask) read 0
+template <int CTRL, int RM, bool BC>
+__device__ __forceinline__ int dpp32(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, RM, 0xF, BC);
+}
+template <int CTRL, int RM, bool BC>
+__device__ __forceinline__ float dppv(float v) {
+  return __builtin_bit_cast(float, dpp32<CTRL, RM, BC>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL, int RM, bool BC>
+__device__ __forceinline__ double dppv(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = dpp32<CTRL, RM, BC>((int)(b & 0xFFFFFFFFLL));
+  const int hi = dpp32<CTRL, RM, BC>((int)(b >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ float lane63(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ double lane63(double v) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFLL), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Segmented scan over the 64 lanes of (f, v), where a set flag starts a new
+// segment after the element: incl_j = f_j ? v_j : incl_{j-1} + v_j.  Returns
+// incl_{j-1} (0 in lane 0); incl_63 goes to out63.  Shifts by 1, 2, 4, 8
+// inside rows of 16 lanes, then row 0's last lane into row 1 (and row 2's
+// into row 3), then lane 31 into rows 2 and 3.
 template <class T>
-__device__ __forceinline__ T wseg_excl(int f, T v) {
-  const int lane = threadIdx.x & 63;
+__device__ __forceinline__ T wseg_excl(int f, T v, T& out63) {
   T sv = v;
   int sf = f;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    T ov = __shfl_up(sv, off, 64);
-    int of = __shfl_up(sf, off, 64);
-    if (lane >= off) {
-      if (!sf) sv = ov + sv;
-      sf |= of;
-    }
+#define PLSS_SEG_STEP(CTRL, RM, BC)              \
+  {                                              \
+    const T ov = dppv<CTRL, RM, BC>(sv);         \
+    const int of = dpp32<CTRL, RM, BC>(sf);      \
+    if (!sf) sv = ov + sv;                       \
+    sf |= of;                                    \
   }
-  T ex = __shfl_up(sv, 1, 64);
-  if (lane == 0) ex = T(0);
-  return ex;
+  PLSS_SEG_STEP(kRowShr1, 0xF, true)
+  PLSS_SEG_STEP(kRowShr2, 0xF, true)
+  PLSS_SEG_STEP(kRowShr4, 0xF, true)
+  PLSS_SEG_STEP(kRowShr8, 0xF, true)
+  PLSS_SEG_STEP(kRowBcast15, 0xA, false)
+  PLSS_SEG_STEP(kRowBcast31, 0xC, false)
+#undef PLSS_SEG_STEP
+  out63 = lane63(sv);
+  return dppv<kWaveShr1, 0xF, true>(sv);
+}
+
+// Entries per lane in a window of c entries: Qw = ceil(c / 64) for lanes
+// below r = c - 64 (Qw - 1), Qw - 1 for the others.
+__device__ __forceinline__ int win_count(int c, int lane) {
+  const int Qw = (c + 63) >> 6;
+  return lane < c - 64 * (Qw - 1) ? Qw : Qw - 1;
+}
+
+// wave range [ws, we): windows of 64 * Q entries, the last one shorter
+__device__ __forceinline__ int range_q(int len) {
+  const int Q = (len + 63) >> 6;
+  return Q > kQmax ? kQmax : (Q < 1 ? 1 : Q);
 }
 
 // first index i in [lo, hi) with a[i] > key (a non-decreasing)
@@ -175,7 +231,117 @@ __global__ void k_st_split(const unsigned* __restrict__ pk, const int* __restric
   }
 }
 
+// Reorder every window of every wave range lane-interleaved: the lane's
+// k-th entry (its entries are consecutive in CSR order) moves to window
+// start + 64 k + lane.  One wave per (segment, wave) range.
+template <class Val>
+__global__ void k_st_interleave(const unsigned* __restrict__ pk, const Val* __restrict__ val,
+                                const int* __restrict__ seg, const int* __restrict__ wsp, long long nseg,
+                                unsigned* __restrict__ opk, Val* __restrict__ oval) {
+  const int lane = threadIdx.x & 63;
+  const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
+  for (long long q = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < nseg * kSWaves; q += nw) {
+    const long long g = q / kSWaves;
+    const int w = (int)(q % kSWaves);
+    const int ws = wsp[q], we = (w + 1 < kSWaves) ? wsp[q + 1] : seg[g + 1];
+    if (we <= ws) continue;
+    const int Q = range_q(we - ws);
+    for (int base = ws; base < we; base += 64 * Q) {
+      const int c = min(64 * Q, we - base);
+      const int Qw = (c + 63) >> 6, r = c - 64 * (Qw - 1);
+      const int mine = lane < r ? Qw : Qw - 1;
+      const int start = lane < r ? lane * Qw : r * Qw + (lane - r) * (Qw - 1);
+      for (int k = 0; k < mine; ++k) {
+        opk[base + 64 * k + lane] = pk[base + start + k];
+        oval[base + 64 * k + lane] = val[base + start + k];
+      }
+    }
+  }
+}
+
 // ------------------------------------------------------------------ product
+
+// One lane-interleaved window of c entries into registers (the lane's
+// entries in CSR order).
+template <class Val>
+__device__ __forceinline__ void load_window(const unsigned* __restrict__ pk, const Val* __restrict__ val, int base,
+                                            int c, unsigned* pv, Val* vv) {
+  const int lane = threadIdx.x & 63;
+  const int mine = c > 0 ? win_count(c, lane) : 0;
+#pragma unroll
+  for (int q = 0; q < kQmax; ++q) {
+    if (q < mine) {
+      pv[q] = __builtin_nontemporal_load(&pk[base + 64 * q + lane]);
+      vv[q] = __builtin_nontemporal_load(&val[base + 64 * q + lane]);
+    } else {
+      pv[q] = 0xFFFFFFFFu;
+      vv[q] = Val(0);
+    }
+  }
+}
+
+// Row sums of one window [base, wend) of a wave range ending at we, added
+// to s_acc.  wc: open row sum carried in from the previous window, and out
+// to the next one.
+template <class Val, class Acc>
+__device__ __forceinline__ void sum_window(const unsigned* __restrict__ pk, int base, int wend, int we,
+                                           const unsigned* pv, const Val* vv, const Acc* __restrict__ xs,
+                                           Acc* s_acc, Acc& wc) {
+  const int lane = threadIdx.x & 63;
+  const int c = wend - base;
+  const int Qw = (c + 63) >> 6, r = c - 64 * (Qw - 1);
+  const int mine = lane < r ? Qw : Qw - 1;
+  const int next_has = (lane + 1 < r ? Qw : Qw - 1) > 0;
+  const int last = Qw > 1 ? 63 : r - 1;  // last lane holding entries
+  // row of the entry after this lane's last one (-1: the range ends there)
+  const int frow = mine > 0 ? (int)(pv[0] >> 16) : -1;
+  const int nb = dpp32<kWaveShl1, 0xF, true>(frow);
+  int nrow = -1;
+  if (lane < 63 && next_has) nrow = nb;
+  else if (lane == last && wend < we) nrow = (int)(__builtin_nontemporal_load(&pk[wend]) >> 16);
+  int cur = -1, fr = 0;
+  bool hend = false;
+  Acc acc = Acc(0), fv = Acc(0);
+#pragma unroll
+  for (int q = 0; q < kQmax; ++q) {
+    if (q < mine) {
+      const int rr = (int)(pv[q] >> 16);
+      const Acc prod = Acc(vv[q]) * xs[pv[q] & 0xFFFFu];
+      if (rr != cur) {
+        if (cur >= 0) {
+          if (!hend) {
+            hend = true;
+            fr = cur;
+            fv = acc;
+          } else {
+            s_acc[cur] += acc;
+          }
+        }
+        acc = Acc(0);
+        cur = rr;
+      }
+      acc += prod;
+    }
+  }
+  if (cur >= 0 && nrow != cur) {
+    if (!hend) {
+      hend = true;
+      fr = cur;
+      fv = acc;
+    } else {
+      s_acc[cur] += acc;
+    }
+    acc = Acc(0);
+  }
+  if (lane == 0) {
+    if (hend) fv = wc + fv;
+    else acc = wc + acc;
+  }
+  Acc out63;
+  const Acc carry = wseg_excl<Acc>(hend ? 1 : 0, acc, out63);
+  if (hend) s_acc[fr] += fv + carry;
+  wc = out63;
+}
 
 // One workgroup per (system, unit).  MODE_RESID: r <- r - A p, partial rho
 // per unit.  MODE_TRANSB: ypart[b] <- A_bᵀ r_b for row block b of A (the
@@ -226,12 +392,28 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 
+  const int* __restrict__ seg = sv.seg + (size_t)u * S;
+  const int* __restrict__ wsp = sv.wsp + (size_t)u * S * kSWaves;
+  auto bounds = [&](int s, int& ws, int& we) {
+    if (s < S) {
+      ws = wsp[s * kSWaves + w];
+      we = (w + 1 < kSWaves) ? wsp[s * kSWaves + w + 1] : seg[s + 1];
+    } else {
+      ws = we = 0;
+    }
+  };
+  // pipeline: bounds of stripes s and s + 1, first window of stripe s
+  int ws0, we0, ws1, we1;
+  unsigned cpv[kQmax];
+  Val cvv[kQmax];
+  bounds(0, ws0, we0);
+  bounds(1, ws1, we1);
+  load_window(pk, val, ws0, min(64 * range_q(we0 - ws0), we0 - ws0), cpv, cvv);
+
   for (int i = threadIdx.x; i < nr; i += kST) s_acc[i] = Acc(0);
   for (int j = threadIdx.x; j < kSW; j += kST) s_x[0][j] = j < xlen ? Acc(x[j]) : Acc(0);
   __syncthreads();
 
-  const int* __restrict__ seg = sv.seg + (size_t)u * S;
-  const int* __restrict__ wsp = sv.wsp + (size_t)u * S * kSWaves;
   for (int s = 0; s < S; ++s) {
     // the next stripe's slice of x travels in registers during this stripe
     Acc nx[kSW / kST];
@@ -240,81 +422,36 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
       const int j = (s + 1) * kSW + q * kST + threadIdx.x;
       nx[q] = (s + 1 < S && j < xlen) ? Acc(x[j]) : Acc(0);
     }
+    int ws2, we2;
+    bounds(s + 2, ws2, we2);
+    unsigned npv[kQmax];
+    Val nvv[kQmax];
+    load_window(pk, val, ws1, min(64 * range_q(we1 - ws1), we1 - ws1), npv, nvv);
+
     const Acc* __restrict__ xs = s_x[s & 1];
-    const int ws = wsp[s * kSWaves + w];
-    const int we = (w + 1 < kSWaves) ? wsp[s * kSWaves + w + 1] : seg[s + 1];
-    const int len = we - ws;
-    if (len > 0) {
-      int Q = (len + 63) >> 6;
-      if (Q > kQmax) Q = kQmax;
+    if (we0 > ws0) {
+      const int Q = range_q(we0 - ws0);
       Acc wc = Acc(0);  // open row sum carried from the previous window
-      for (int base = ws; base < we; base += 64 * Q) {
-        const int wend = min(base + 64 * Q, we);
-        const int q0 = base + lane * Q;
+      sum_window<Val, Acc>(pk, ws0, min(ws0 + 64 * Q, we0), we0, cpv, cvv, xs, s_acc, wc);
+      for (int base = ws0 + 64 * Q; base < we0; base += 64 * Q) {
+        const int wend = min(base + 64 * Q, we0);
         unsigned pv[kQmax];
         Val vv[kQmax];
-#pragma unroll
-        for (int q = 0; q < kQmax; ++q) {
-          if (q < Q && q0 + q < wend) {
-            pv[q] = __builtin_nontemporal_load(&pk[q0 + q]);
-            vv[q] = __builtin_nontemporal_load(&val[q0 + q]);
-          } else {
-            pv[q] = 0xFFFFFFFFu;
-            vv[q] = Val(0);
-          }
-        }
-        // row of the entry after this lane's last one (-1: the range ends)
-        const int frow = q0 < wend ? (int)(pv[0] >> 16) : -1;
-        const int nb = __shfl_down(frow, 1, 64);
-        int nrow = -1;
-        if (q0 + Q < wend) nrow = nb;
-        else if (q0 + Q == wend && wend < we) nrow = (int)(__builtin_nontemporal_load(&pk[wend]) >> 16);
-        int cur = -1, fr = 0;
-        bool hend = false;
-        Acc acc = Acc(0), fv = Acc(0);
-#pragma unroll
-        for (int q = 0; q < kQmax; ++q) {
-          if (q < Q && q0 + q < wend) {
-            const int r = (int)(pv[q] >> 16);
-            const Acc prod = Acc(vv[q]) * xs[pv[q] & 0xFFFFu];
-            if (r != cur) {
-              if (cur >= 0) {
-                if (!hend) {
-                  hend = true;
-                  fr = cur;
-                  fv = acc;
-                } else {
-                  s_acc[cur] += acc;
-                }
-              }
-              acc = Acc(0);
-              cur = r;
-            }
-            acc += prod;
-          }
-        }
-        if (cur >= 0 && nrow != cur) {
-          if (!hend) {
-            hend = true;
-            fr = cur;
-            fv = acc;
-          } else {
-            s_acc[cur] += acc;
-          }
-          acc = Acc(0);
-        }
-        if (lane == 0) {
-          if (hend) fv = wc + fv;
-          else acc = wc + acc;
-        }
-        const Acc carry = wseg_excl<Acc>(hend ? 1 : 0, acc);
-        if (hend) s_acc[fr] += fv + carry;
-        const Acc incl = hend ? acc : carry + acc;
-        wc = __shfl(incl, 63, 64);
+        load_window(pk, val, base, wend - base, pv, vv);
+        sum_window<Val, Acc>(pk, base, wend, we0, pv, vv, xs, s_acc, wc);
       }
     }
 #pragma unroll
     for (int q = 0; q < kSW / kST; ++q) s_x[(s + 1) & 1][q * kST + threadIdx.x] = nx[q];
+#pragma unroll
+    for (int q = 0; q < kQmax; ++q) {
+      cpv[q] = npv[q];
+      cvv[q] = nvv[q];
+    }
+    ws0 = ws1;
+    we0 = we1;
+    ws1 = ws2;
+    we1 = we2;
     __syncthreads();
   }
 
@@ -402,6 +539,19 @@ void st_scatter(const int* ptr, const int* idx, const void* val, bool f32, int n
 void st_split(const unsigned* pk, const int* d_seg, long long nseg, int* d_wsp, hipStream_t s) {
   if (nseg <= 0) return;
   k_st_split<<<st_grid(nseg * kSWaves, 256), 256, 0, s>>>(pk, d_seg, nseg, d_wsp);
+  PLSS_HIP(hipGetLastError());
+}
+
+void st_interleave(const unsigned* pk, const void* val, bool f32, const int* d_seg, const int* d_wsp, long long nseg,
+                   unsigned* opk, void* oval, hipStream_t s) {
+  if (nseg <= 0) return;
+  const int grid = st_grid(nseg * kSWaves * 64, 256);
+  if (f32)
+    k_st_interleave<float><<<grid, 256, 0, s>>>(pk, static_cast<const float*>(val), d_seg, d_wsp, nseg, opk,
+                                               static_cast<float*>(oval));
+  else
+    k_st_interleave<double><<<grid, 256, 0, s>>>(pk, static_cast<const double*>(val), d_seg, d_wsp, nseg, opk,
+                                                static_cast<double*>(oval));
   PLSS_HIP(hipGetLastError());
 }
 
