@@ -50,17 +50,17 @@ def bytes_model(m, n, nnz, f32=False):
     return {"spmv": spmv, "spmvt": spmvt, "update": upd, "iter": spmv + spmvt + upd}
 
 
-def recorded_traffic(kernel_index):
+def recorded_traffic(kernel_index, layout):
     """Calibrated HBM bytes per launch of the dominant kernel from the
-    committed rocprofv3 counter passes, or None when the kernel source has
-    changed since they were taken."""
+    committed rocprofv3 counter passes, or None when the kernel source (or
+    the layout) differs from the one the counters were taken with."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "large_fp64_traffic.txt")
-    src = os.path.join(ROOT, "paper_2207_07615_amd", "csrc", "kernels.hip")
     try:
         kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
+        src = os.path.join(ROOT, "paper_2207_07615_amd", "csrc", kv["source"])
         sha = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
-        if kv.get("kernels_hip_sha1_12") != sha:
+        if kv.get("source_sha1_12") != sha or kv.get("layout") != layout:
             return None
         sfx = "" if kernel_index == 0 else "_t"
         return (float(kv["fetch_kib" + sfx]) * float(kv["fetch_scale"]) +
@@ -69,7 +69,7 @@ def recorded_traffic(kernel_index):
         return None
 
 
-def cpu_baseline(sysm, iters=12):
+def cpu_baseline(sysm, iters=60):
     """The oracle (Algorithm 1 in float64, SciPy sparse products) on the
     first `iters` iterations of the same system, single-threaded."""
     try:
@@ -470,12 +470,18 @@ def main():
         "p99_ms": lat_ms[min(len(lat_ms) - 1, int(math.ceil(0.99 * len(lat_ms))) - 1)],
         "hbm_gbps_iteration": bm["iter"] * iters_per_s / 1e9,
         "hbm_gbps_spmv_pair": pair_gbs,
-        "kernel_ms": {"spmv": avg[0], "spmvt": avg[1], "step": avg[2], "update": avg[3]},
+        "kernel_ms": {"spmv": avg[0], "spmvt": avg[1], "blocksum_step": avg[2], "update": avg[3]},
         "relres_true": relres_true,
         "rel_err_vs_xstar": err_xstar,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(dom),
-                     "kernel": "spmv (r -= A p, rho)" if dom == 0 else "spmvt (y = A^T r, phi)",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": recorded_traffic(dom, "stripes" if layout["a_stripes"] and layout["t_stripes"]
+                                                 else "tiles" if not (layout["a_stripes"] or layout["t_stripes"])
+                                                 else "mixed"),
+                     "kernel": (("k_sspmv RESID" if layout["a_stripes"] else "k_spmv RESID") +
+                                " (r -= A p, partial rho)") if dom == 0 else
+                               (("k_sspmv TRANSB (row-block products A_b^T r_b)" if layout["t_stripes"]
+                                 else "k_spmv TRANS (y = A^T r)")),
                      "algorithmic_bytes_per_launch": dom_bytes},
     }
 

@@ -193,8 +193,9 @@ plss_status plss_solve_multi(plss_handle* h, const plss_matrix* A, int32_t nrhs,
 
 /* Per-kernel device time accumulated while opts.timing was set, and the
  * number of launches: index 0 = product with A (r <- r - A p), 1 = product
- * with Aᵀ (y <- Aᵀ r), 2 = step scalars, 3 = vector update.  Resets the
- * counters. */
+ * with Aᵀ (y <- Aᵀ r; with row blocks of Aᵀ, the block products), 2 = sum of
+ * the block products (when there are row blocks) and step scalars, 3 =
+ * vector update.  Resets the counters. */
 plss_status plss_kernel_times(plss_handle* h, double* ms4, int64_t* launches4);
 
 /* ---- request loop (continuous batching) ----

@@ -253,9 +253,9 @@ void ListSet::iteration(const Desc* dd, hipStream_t s, hipEvent_t* ev) const {
     launch_spmv(g.key >= 1000 ? MODE_TRANSB : MODE_TRANS, k >= 100, k % 100, dd, g.list, g.n, 1, s);
   }
   for (auto& g : sb) launch_sspmv(MODE_TRANSB, g.key == 1, dd, g.list, g.n, 1, s);
+  if (ev) PLSS_HIP(hipEventRecord(ev[2], s));
   if (any_blk)
     for (auto& g : u) launch_ycomb(g.key == 1, dd, g.list, g.n, s);
-  if (ev) PLSS_HIP(hipEventRecord(ev[2], s));
   launch_step(dd, sys, nsys, s);
   if (ev) PLSS_HIP(hipEventRecord(ev[3], s));
   for (auto& g : u) launch_update(g.key == 1, dd, g.list, g.n, s);

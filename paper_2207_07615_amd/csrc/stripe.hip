@@ -22,9 +22,9 @@
 // every load instruction of the wave reads 64 consecutive entries.  Stripes
 // are applied in order, so each row sum has one fixed order: the product is
 // deterministic and does not depend on which other systems share a launch.
-// The next stripe's wave bounds are read two stripes ahead and its first
-// window one stripe ahead, so their memory latency overlaps the current
-// stripe's arithmetic.
+// Wave bounds are read three stripes ahead and first windows two stripes
+// ahead, so their memory latency overlaps the arithmetic of the stripes in
+// between.
 #include "kernels.hpp"
 
 namespace plss {
@@ -33,7 +33,7 @@ namespace {
 
 constexpr int kST = kSThreads;       // threads of the striped workgroups
 constexpr int kSWaves = kST / 64;    // waves per striped workgroup
-constexpr int kQmax = 8;             // entries per lane of one window
+constexpr int kQmax = 6;             // entries per lane of one window
 
 template <class T>
 __device__ __forceinline__ T swsum(T v) {
@@ -99,6 +99,17 @@ __device__ __forceinline__ T wseg_excl(int f, T v, T& out63) {
   out63 = lane63(sv);
   return dppv<kWaveShr1, 0xF, true>(sv);
 }
+
+// s_acc[i] += v.  Each row has a single writer per stripe (wave ranges and
+// lane runs are row-aligned, or carried to the lane that ends the row), so
+// the result is the plain sum in a fixed order either way.  For float64 the
+// LDS atomic add does the read-modify-write in one instruction and measured
+// faster than a separate read and write; for float32 the atomic add measured
+// twice as slow on this access pattern, so float sums use the plain form.
+__device__ __forceinline__ void lds_add(double* p, double v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void lds_add(float* p, float v) { *p += v; }
 
 // Entries per lane in a window of c entries: Qw = ceil(c / 64) for lanes
 // below r = c - 64 (Qw - 1), Qw - 1 for the others.
@@ -314,7 +325,7 @@ __device__ __forceinline__ void sum_window(const unsigned* __restrict__ pk, int 
             fr = cur;
             fv = acc;
           } else {
-            s_acc[cur] += acc;
+            lds_add(&s_acc[cur], acc);
           }
         }
         acc = Acc(0);
@@ -329,7 +340,7 @@ __device__ __forceinline__ void sum_window(const unsigned* __restrict__ pk, int 
       fr = cur;
       fv = acc;
     } else {
-      s_acc[cur] += acc;
+      lds_add(&s_acc[cur], acc);
     }
     acc = Acc(0);
   }
@@ -339,7 +350,7 @@ __device__ __forceinline__ void sum_window(const unsigned* __restrict__ pk, int 
   }
   Acc out63;
   const Acc carry = wseg_excl<Acc>(hend ? 1 : 0, acc, out63);
-  if (hend) s_acc[fr] += fv + carry;
+  if (hend) lds_add(&s_acc[fr], fv + carry);
   wc = out63;
 }
 
@@ -402,13 +413,15 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
       ws = we = 0;
     }
   };
-  // pipeline: bounds of stripes s and s + 1, first window of stripe s
-  int ws0, we0, ws1, we1;
-  unsigned cpv[kQmax];
-  Val cvv[kQmax];
+  // pipeline: bounds of stripes s, s + 1, s + 2; first windows of s and s + 1
+  int ws0, we0, ws1, we1, ws2, we2;
+  unsigned cpv[kQmax], npv[kQmax];
+  Val cvv[kQmax], nvv[kQmax];
   bounds(0, ws0, we0);
   bounds(1, ws1, we1);
+  bounds(2, ws2, we2);
   load_window(pk, val, ws0, min(64 * range_q(we0 - ws0), we0 - ws0), cpv, cvv);
+  load_window(pk, val, ws1, min(64 * range_q(we1 - ws1), we1 - ws1), npv, nvv);
 
   for (int i = threadIdx.x; i < nr; i += kST) s_acc[i] = Acc(0);
   for (int j = threadIdx.x; j < kSW; j += kST) s_x[0][j] = j < xlen ? Acc(x[j]) : Acc(0);
@@ -422,11 +435,11 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
       const int j = (s + 1) * kSW + q * kST + threadIdx.x;
       nx[q] = (s + 1 < S && j < xlen) ? Acc(x[j]) : Acc(0);
     }
-    int ws2, we2;
-    bounds(s + 2, ws2, we2);
-    unsigned npv[kQmax];
-    Val nvv[kQmax];
-    load_window(pk, val, ws1, min(64 * range_q(we1 - ws1), we1 - ws1), npv, nvv);
+    int ws3, we3;
+    bounds(s + 3, ws3, we3);
+    unsigned mpv[kQmax];
+    Val mvv[kQmax];
+    load_window(pk, val, ws2, min(64 * range_q(we2 - ws2), we2 - ws2), mpv, mvv);
 
     const Acc* __restrict__ xs = s_x[s & 1];
     if (we0 > ws0) {
@@ -447,11 +460,15 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
     for (int q = 0; q < kQmax; ++q) {
       cpv[q] = npv[q];
       cvv[q] = nvv[q];
+      npv[q] = mpv[q];
+      nvv[q] = mvv[q];
     }
     ws0 = ws1;
     we0 = we1;
     ws1 = ws2;
     we1 = we2;
+    ws2 = ws3;
+    we2 = we3;
     __syncthreads();
   }
 
