@@ -111,6 +111,21 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
 }
 __device__ __forceinline__ void lds_add(float* p, float v) { *p += v; }
 
+// Streaming load through a global-address-space pointer: the store's arrays
+// are reached through the descriptor, so the compiler would otherwise emit
+// flat loads, which also count against the LDS wait counter and make every
+// LDS wait drain the prefetched entries.
+template <class T>
+__device__ __forceinline__ T gload_nt(const T* p) {
+  using GP = const __attribute__((address_space(1))) T*;
+  return __builtin_nontemporal_load((GP)p);
+}
+template <class T>
+__device__ __forceinline__ T gload(const T* p) {
+  using GP = const __attribute__((address_space(1))) T*;
+  return *(GP)p;
+}
+
 // Entries per lane in a window of c entries: Qw = ceil(c / 64) for lanes
 // below r = c - 64 (Qw - 1), Qw - 1 for the others.
 __device__ __forceinline__ int win_count(int c, int lane) {
@@ -282,8 +297,8 @@ __device__ __forceinline__ void load_window(const unsigned* __restrict__ pk, con
 #pragma unroll
   for (int q = 0; q < kQmax; ++q) {
     if (q < mine) {
-      pv[q] = __builtin_nontemporal_load(&pk[base + 64 * q + lane]);
-      vv[q] = __builtin_nontemporal_load(&val[base + 64 * q + lane]);
+      pv[q] = gload_nt(&pk[base + 64 * q + lane]);
+      vv[q] = gload_nt(&val[base + 64 * q + lane]);
     } else {
       pv[q] = 0xFFFFFFFFu;
       vv[q] = Val(0);
@@ -309,29 +324,28 @@ __device__ __forceinline__ void sum_window(const unsigned* __restrict__ pk, int 
   const int nb = dpp32<kWaveShl1, 0xF, true>(frow);
   int nrow = -1;
   if (lane < 63 && next_has) nrow = nb;
-  else if (lane == last && wend < we) nrow = (int)(__builtin_nontemporal_load(&pk[wend]) >> 16);
+  else if (lane == last && wend < we) nrow = (int)(gload_nt(&pk[wend]) >> 16);
   int cur = -1, fr = 0;
   bool hend = false;
   Acc acc = Acc(0), fv = Acc(0);
+  // all gathers of the window first (back to back in LDS); a slot without an
+  // entry reads a valid address and its product is never used
+  Acc prods[kQmax];
+#pragma unroll
+  for (int q = 0; q < kQmax; ++q) prods[q] = Acc(vv[q]) * xs[pv[q] & (kSW - 1)];
 #pragma unroll
   for (int q = 0; q < kQmax; ++q) {
     if (q < mine) {
       const int rr = (int)(pv[q] >> 16);
-      const Acc prod = Acc(vv[q]) * xs[pv[q] & 0xFFFFu];
-      if (rr != cur) {
-        if (cur >= 0) {
-          if (!hend) {
-            hend = true;
-            fr = cur;
-            fv = acc;
-          } else {
-            lds_add(&s_acc[cur], acc);
-          }
-        }
-        acc = Acc(0);
-        cur = rr;
-      }
-      acc += prod;
+      const bool brk = rr != cur;
+      const bool ended = brk && cur >= 0;  // the run of `cur` ends before this entry
+      if (ended && hend) lds_add(&s_acc[cur], acc);
+      const bool first = ended && !hend;   // the lane's first run end waits for the carry
+      fv = first ? acc : fv;
+      fr = first ? cur : fr;
+      hend = hend || ended;
+      acc = brk ? prods[q] : acc + prods[q];
+      cur = rr;
     }
   }
   if (cur >= 0 && nrow != cur) {
@@ -407,38 +421,41 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
   const int* __restrict__ wsp = sv.wsp + (size_t)u * S * kSWaves;
   auto bounds = [&](int s, int& ws, int& we) {
     if (s < S) {
-      ws = wsp[s * kSWaves + w];
-      we = (w + 1 < kSWaves) ? wsp[s * kSWaves + w + 1] : seg[s + 1];
+      ws = gload(&wsp[s * kSWaves + w]);
+      we = (w + 1 < kSWaves) ? gload(&wsp[s * kSWaves + w + 1]) : gload(&seg[s + 1]);
     } else {
       ws = we = 0;
     }
   };
-  // pipeline: bounds of stripes s, s + 1, s + 2; first windows of s and s + 1
-  int ws0, we0, ws1, we1, ws2, we2;
-  unsigned cpv[kQmax], npv[kQmax];
-  Val cvv[kQmax], nvv[kQmax];
-  bounds(0, ws0, we0);
-  bounds(1, ws1, we1);
-  bounds(2, ws2, we2);
-  load_window(pk, val, ws0, min(64 * range_q(we0 - ws0), we0 - ws0), cpv, cvv);
-  load_window(pk, val, ws1, min(64 * range_q(we1 - ws1), we1 - ws1), npv, nvv);
+  // Three register sets rotate over the stripes: at stripe s, set "cur"
+  // holds stripe s (bounds and first window), the next set stripe s + 1, and
+  // the third receives stripe s + 2's first window while stripe s is summed;
+  // cur's bounds then take stripe s + 3.  The loop is unrolled by three so
+  // the sets keep fixed registers instead of being copied every stripe.
+  int wsA, weA, wsB, weB, wsC, weC;
+  unsigned pA[kQmax], pB[kQmax], pC[kQmax];
+  Val vA[kQmax], vB[kQmax], vC[kQmax];
+  bounds(0, wsA, weA);
+  bounds(1, wsB, weB);
+  bounds(2, wsC, weC);
+  load_window(pk, val, wsA, min(64 * range_q(weA - wsA), weA - wsA), pA, vA);
+  load_window(pk, val, wsB, min(64 * range_q(weB - wsB), weB - wsB), pB, vB);
 
   for (int i = threadIdx.x; i < nr; i += kST) s_acc[i] = Acc(0);
-  for (int j = threadIdx.x; j < kSW; j += kST) s_x[0][j] = j < xlen ? Acc(x[j]) : Acc(0);
+  for (int j = threadIdx.x; j < kSW; j += kST) s_x[0][j] = j < xlen ? Acc(gload(&x[j])) : Acc(0);
   __syncthreads();
 
-  for (int s = 0; s < S; ++s) {
+  auto stripe = [&](int s, int& ws0, int& we0, const unsigned* cpv, const Val* cvv, int ws2, int we2,
+                    unsigned* mpv, Val* mvv) {
     // the next stripe's slice of x travels in registers during this stripe
     Acc nx[kSW / kST];
 #pragma unroll
     for (int q = 0; q < kSW / kST; ++q) {
       const int j = (s + 1) * kSW + q * kST + threadIdx.x;
-      nx[q] = (s + 1 < S && j < xlen) ? Acc(x[j]) : Acc(0);
+      nx[q] = (s + 1 < S && j < xlen) ? Acc(gload(&x[j])) : Acc(0);
     }
     int ws3, we3;
     bounds(s + 3, ws3, we3);
-    unsigned mpv[kQmax];
-    Val mvv[kQmax];
     load_window(pk, val, ws2, min(64 * range_q(we2 - ws2), we2 - ws2), mpv, mvv);
 
     const Acc* __restrict__ xs = s_x[s & 1];
@@ -456,20 +473,16 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
     }
 #pragma unroll
     for (int q = 0; q < kSW / kST; ++q) s_x[(s + 1) & 1][q * kST + threadIdx.x] = nx[q];
-#pragma unroll
-    for (int q = 0; q < kQmax; ++q) {
-      cpv[q] = npv[q];
-      cvv[q] = nvv[q];
-      npv[q] = mpv[q];
-      nvv[q] = mvv[q];
-    }
-    ws0 = ws1;
-    we0 = we1;
-    ws1 = ws2;
-    we1 = we2;
-    ws2 = ws3;
-    we2 = we3;
+    ws0 = ws3;
+    we0 = we3;
     __syncthreads();
+  };
+  for (int s = 0; s < S; s += 3) {
+    stripe(s, wsA, weA, pA, vA, wsC, weC, pC, vC);
+    if (s + 1 >= S) break;
+    stripe(s + 1, wsB, weB, pB, vB, wsA, weA, pA, vA);
+    if (s + 2 >= S) break;
+    stripe(s + 2, wsC, weC, pC, vC, wsB, weB, pB, vB);
   }
 
   // epilogue over the unit's rows
