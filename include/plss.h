@@ -138,11 +138,13 @@ plss_status plss_matrix_autotune(plss_handle* h, plss_matrix* A, int32_t* csr_wi
  *  - Tiles (0): the CSR / CSC tile tables; every product gathers its input
  *    vector from memory.
  *  - Stripes (1): a striped copy of the direction.  One workgroup owns a unit
- *    of at most 8192 rows and keeps their sums in LDS while the input vector
- *    passes through LDS in stripes of 4096 entries; the entries of a unit are
- *    stored stripe by stripe.  For Aᵀ the rows of A are first split into 8
- *    blocks (one per XCD) and each block gets its own striped store; the block
- *    products are summed in block order.
+ *    of rows and keeps their sums in LDS while the input vector passes
+ *    through LDS in stripes; the entries of a unit are stored stripe by
+ *    stripe.  Products with A: units of at most 8192 rows, stripes of 4096
+ *    entries.  For Aᵀ the rows of A are first split into 8 blocks (one per
+ *    XCD) and each block gets its own striped store (units of at most 16384
+ *    rows, stripes of 2048 entries); the block products are summed in block
+ *    order.
  * Both layouts give deterministic sums (a fixed order per matrix) and the
  * same results up to rounding.  plss_matrix_create picks stripes for a
  * direction when the matrix has at least 2^23 entries and every unit reading
@@ -150,15 +152,16 @@ plss_status plss_matrix_autotune(plss_handle* h, plss_matrix* A, int32_t* csr_wi
 typedef struct {
   int32_t a_stripes;    /* products with A use the striped store */
   int32_t t_stripes;    /* products with Aᵀ use the striped row-block stores */
-  int32_t unit_rows;    /* rows per unit, 1..8192; 0 = chosen from the shape */
+  int32_t unit_rows;    /* rows per unit, 1..16384 (at most 8192 are used for A);
+                           0 = chosen from the shape */
 } plss_layout;
 /* Read (got) and / or change (want) the layout of A; want = NULL only reads.
  * Building a striped store takes about (4 + value bytes) per entry of device
  * memory per direction and a few milliseconds per 10^8 entries; dropping one
  * frees it.  plss_spmv and the residual-sketch solves use the layout in
  * force at the time of the call (the identity and mixed sketches always use
- * the tiles).  Errors: EINVAL for unit_rows outside [0, 8192] or more than
- * 8192 stripes (n or m/8 above 33.5 million), ENOMEM; on error the
+ * the tiles).  Errors: EINVAL for unit_rows outside [0, 16384] or more than
+ * 8192 stripes (n above 33.5 million or m/8 above 16.7 million), ENOMEM; on error the
  * directions whose store could not be built fall back to tiles. */
 plss_status plss_matrix_layout(plss_handle* h, plss_matrix* A, const plss_layout* want, plss_layout* got);
 

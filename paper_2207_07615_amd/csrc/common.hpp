@@ -39,13 +39,17 @@ enum SpmvMode : int {
 
 constexpr int kMaxBlk = 8;         // row blocks of the transposed store (one per XCD)
 
-// Striped store (stripe.hip): a work unit of at most kRBmax rows keeps its
-// row sums in LDS while the gathered vector passes through LDS in stripes
-// of kSW entries; kSThreads threads per unit.
-constexpr int kSW = 4096;
-constexpr int kRBmax = 8192;
+// Striped store (stripe.hip): a work unit keeps its row sums in LDS while the
+// gathered vector passes through LDS in stripes; kSThreads threads per unit.
+// Stores of A: stripes of 4096 columns, units of at most 8192 rows.  Row-block
+// stores of Aᵀ: stripes of 2048, units of at most 16384 rows, so that the
+// product with Aᵀ runs one unit per CU (the same LDS, 2 x 16 KB + 128 KB).
+constexpr int kSWA = 4096, kRBA = 8192;
+constexpr int kSWT = 2048, kRBT = 16384;
 constexpr int kSThreads = 1024;
 constexpr int kMaxStripes = 8192;  // stripes per store (cursor table of the builder in LDS)
+constexpr int kStorePad = 64;      // entries allocated past the end of a striped store: a
+                                   // window's last slot is loaded by every lane of the wave
 
 struct StripeView {
   const unsigned* pk;          // entries: (row in unit) << 16 | (column in stripe)
@@ -55,6 +59,7 @@ struct StripeView {
   const int* wsp;              // 16 row-aligned wave starts per segment
   int nunits, S;
   int colbase, ncols;          // columns [colbase, colbase + ncols) of the gathered vector
+  int sw;                      // stripe width (kSWA or kSWT)
 };
 
 struct State {

@@ -51,10 +51,10 @@ void launch_ycomb(bool f32, const Desc* d, const int2* ulist, int n, hipStream_t
 
 namespace plss {
 // striped store (stripe.hip): build steps and the product
-void st_count(const int* ptr, const int* idx, int nunits, const int* d_urow, int S, int colbase, int* d_cnt,
+void st_count(const int* ptr, const int* idx, int nunits, const int* d_urow, int S, int colbase, int sw, int* d_cnt,
               hipStream_t s);
 void st_scatter(const int* ptr, const int* idx, const void* val, bool f32, int nunits, const int* d_urow,
-                const int* d_seg, int S, int colbase, unsigned* opk, void* oval, hipStream_t s);
+                const int* d_seg, int S, int colbase, int sw, unsigned* opk, void* oval, hipStream_t s);
 void st_split(const unsigned* pk, const int* d_seg, long long nseg, int* d_wsp, hipStream_t s);
 void st_interleave(const unsigned* pk, const void* val, bool f32, const int* d_seg, const int* d_wsp, long long nseg,
                    unsigned* opk, void* oval, hipStream_t s);

@@ -100,15 +100,15 @@ size_t matrix_footprint(long long m, long long n, long long nnz, bool f32) {
 
 // ------------------------------------------------------------------ striped layout
 
-int auto_unit_rows(long long rows, int nblk) {
+int auto_unit_rows(long long rows, int nblk, int rbmax) {
   // units per block: enough for the 256 CUs over all blocks, rounded so that
-  // every XCD gets the same count, and at most kRBmax rows each
+  // every XCD gets the same count, and at most rbmax rows each
   const long long per_round = (256 + nblk - 1) / nblk;
-  long long nu = (rows + kRBmax - 1) / kRBmax;
+  long long nu = (rows + rbmax - 1) / rbmax;
   nu = (nu + per_round - 1) / per_round * per_round;
   long long R = (rows + nu - 1) / nu;
   R = std::max<long long>(R, std::min<long long>(rows, 512));
-  return (int)std::max<long long>(1, std::min<long long>(R, kRBmax));
+  return (int)std::max<long long>(1, std::min<long long>(R, rbmax));
 }
 
 // Stripes pay when the gathered vector is re-read less than the entries are
@@ -119,15 +119,15 @@ void auto_layout(long long m, long long n, long long nnz, bool f32, bool* a_stri
   if (nnz < (1LL << 23)) return;
   const double entry_bytes = (double)nnz * (4.0 + vb);
   {
-    const int R = auto_unit_rows(m, 1);
+    const int R = auto_unit_rows(m, 1, kRBA);
     const long long nu = (m + R - 1) / R;
-    const long long S = (n + kSW - 1) / kSW;
+    const long long S = (n + kSWA - 1) / kSWA;
     if (S <= kMaxStripes && nu >= 128 && (double)nu * (double)n * vb <= 0.75 * entry_bytes) *a_stripes = true;
   }
   if ((double)m * vb > (double)(3u << 20)) {
-    const int R = auto_unit_rows(n, kMaxBlk);
+    const int R = auto_unit_rows(n, kMaxBlk, kRBT);
     const long long nu = (long long)kMaxBlk * ((n + R - 1) / R);
-    const long long S = (m / kMaxBlk + kSW) / kSW;
+    const long long S = (m / kMaxBlk + kSWT) / kSWT;
     if (S <= kMaxStripes && nu >= 128 && (double)nu * ((double)m / kMaxBlk) * vb <= entry_bytes) *t_stripes = true;
   }
 }
@@ -151,16 +151,17 @@ void fill_stripe_view(const PlssStripes& st, StripeView* v) {
   v->S = st.S;
   v->colbase = st.colbase;
   v->ncols = st.ncols;
+  v->sw = st.sw;
 }
 
 // Striped copy of the CSR direction `src` restricted to columns
 // [colbase, colbase + ncols) (all of its entries lie there).
-static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, bool f32, PlssStripes& out,
+static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, int sw, bool f32, PlssStripes& out,
                           hipStream_t s) {
   const int rows = src.nrows;
   const long long nnz = src.h_ptr[rows];
   const int nunits = (rows + R - 1) / R;
-  const int S = (ncols + kSW - 1) / kSW;
+  const int S = (ncols + sw - 1) / sw;
   if (S > kMaxStripes) throw InvalidArg{"too many columns for the striped layout"};
   const long long nseg = (long long)nunits * S;
   if (nseg * 16 >= (1LL << 31) - 1) throw InvalidArg{"too many stripe segments: raise unit_rows"};
@@ -179,7 +180,7 @@ static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, boo
     cnt = static_cast<int*>(dmalloc(sizeof(int) * (size_t)std::max<long long>(nseg, 1)));
     work = dmalloc(sizeof(long long) * (size_t)((nseg + 1023) / 1024 + 2));
     PLSS_HIP(hipMemcpyAsync(st.urow, urow.data(), sizeof(int) * urow.size(), hipMemcpyHostToDevice, s));
-    st_count(src.ptr, src.idx, nunits, st.urow, S, colbase, cnt, s);
+    st_count(src.ptr, src.idx, nunits, st.urow, S, colbase, sw, cnt, s);
     scan_counts(cnt, (int)nseg, st.seg, work, s);
     int total = 0;
     PLSS_HIP(hipMemcpyAsync(&total, st.seg + nseg, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -188,13 +189,15 @@ static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, boo
       set_error("striped store: entry count mismatch");
       throw DeviceError();
     }
-    st_scatter(src.ptr, src.idx, src.val, f32, nunits, st.urow, st.seg, S, colbase, st.pk, st.val, s);
+    st_scatter(src.ptr, src.idx, src.val, f32, nunits, st.urow, st.seg, S, colbase, sw, st.pk, st.val, s);
     st_split(st.pk, st.seg, nseg, st.wsp, s);
     // lane-interleaved windows (out of place, then the CSR-ordered copy goes)
-    unsigned* ipk = static_cast<unsigned*>(dmalloc(sizeof(unsigned) * (size_t)std::max<long long>(nnz, 1)));
+    unsigned* ipk = static_cast<unsigned*>(dmalloc(sizeof(unsigned) * (size_t)(nnz + kStorePad)));
     void* ival = nullptr;
     try {
-      ival = dmalloc(vb * (size_t)std::max<long long>(nnz, 1));
+      ival = dmalloc(vb * (size_t)(nnz + kStorePad));
+      PLSS_HIP(hipMemsetAsync(ipk + nnz, 0, sizeof(unsigned) * kStorePad, s));
+      PLSS_HIP(hipMemsetAsync(static_cast<char*>(ival) + vb * nnz, 0, vb * kStorePad, s));
       st_interleave(st.pk, st.val, f32, st.seg, st.wsp, nseg, ipk, ival, s);
       PLSS_HIP(hipStreamSynchronize(s));
     } catch (...) {
@@ -219,8 +222,9 @@ static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, boo
   st.colbase = colbase;
   st.ncols = ncols;
   st.unit_rows = R;
+  st.sw = sw;
   st.nnz = nnz;
-  st.bytes = (size_t)nnz * (4 + vb) + sizeof(int) * (size_t)(nunits + 1 + (nseg + 1) + nseg * 16);
+  st.bytes = (size_t)(nnz + kStorePad) * (4 + vb) + sizeof(int) * (size_t)(nunits + 1 + (nseg + 1) + nseg * 16);
   free_stripes(out);
   out = st;
 }
@@ -237,13 +241,13 @@ static void recount_bytes(plss_matrix* M) {
 }
 
 void matrix_set_layout(plss_matrix* M, bool a_stripes, bool t_stripes, int unit_rows, hipStream_t s) {
-  if (unit_rows < 0 || unit_rows > kRBmax) throw InvalidArg{"unit_rows must be in [0, 8192]"};
+  if (unit_rows < 0 || unit_rows > kRBT) throw InvalidArg{"unit_rows must be in [0, 16384]"};
   try {
     if (a_stripes) {
-      const int R = unit_rows ? unit_rows : auto_unit_rows(M->m, 1);
+      const int R = unit_rows ? std::min(unit_rows, kRBA) : auto_unit_rows(M->m, 1, kRBA);
       if (!M->a_striped || M->SA.unit_rows != R) {
         M->a_striped = false;
-        build_stripes(M->A, 0, (int)M->n, R, M->f32, M->SA, s);
+        build_stripes(M->A, 0, (int)M->n, R, kSWA, M->f32, M->SA, s);
       }
     } else {
       free_stripes(M->SA);
@@ -251,11 +255,11 @@ void matrix_set_layout(plss_matrix* M, bool a_stripes, bool t_stripes, int unit_
     M->a_striped = a_stripes;
     if (t_stripes) {
       build_row_blocks(M, s, true);
-      const int R = unit_rows ? unit_rows : auto_unit_rows(M->n, M->nblk);
+      const int R = unit_rows ? std::min(unit_rows, kRBT) : auto_unit_rows(M->n, M->nblk, kRBT);
       if (!M->t_striped || M->SB[0].unit_rows != R) {
         M->t_striped = false;
         for (int b = 0; b < M->nblk; ++b)
-          build_stripes(M->TB[b], M->rb[b], M->rb[b + 1] - M->rb[b], R, M->f32, M->SB[b], s);
+          build_stripes(M->TB[b], M->rb[b], M->rb[b + 1] - M->rb[b], R, kSWT, M->f32, M->SB[b], s);
       }
     } else {
       for (int b = 0; b < kMaxBlk; ++b) free_stripes(M->SB[b]);

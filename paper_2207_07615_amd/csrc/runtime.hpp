@@ -24,14 +24,14 @@ struct PlssDir {
 };
 
 // A striped store of one direction (stripe.hip): units of unit_rows rows,
-// stripes of kSW columns of the gathered vector.
+// stripes of sw columns of the gathered vector.
 struct PlssStripes {
   unsigned* pk = nullptr;  // nnz packed (row in unit, column in stripe)
   void* val = nullptr;     // nnz values (storage precision)
   int* urow = nullptr;     // nunits + 1
   int* seg = nullptr;      // nunits * S + 1
   int* wsp = nullptr;      // nunits * S * 16
-  int nunits = 0, S = 0, colbase = 0, ncols = 0, unit_rows = 0;
+  int nunits = 0, S = 0, colbase = 0, ncols = 0, unit_rows = 0, sw = 0;
   long long nnz = 0;
   size_t bytes = 0;
 };
@@ -89,7 +89,7 @@ size_t matrix_footprint(long long m, long long n, long long nnz, bool f32);
 void matrix_set_layout(plss_matrix* M, bool a_stripes, bool t_stripes, int unit_rows, hipStream_t s);
 // Layout chosen from the shape at creation.
 void auto_layout(long long m, long long n, long long nnz, bool f32, bool* a_stripes, bool* t_stripes);
-int auto_unit_rows(long long rows, int nblk);
+int auto_unit_rows(long long rows, int nblk, int rbmax);
 void fill_stripe_view(const PlssStripes& st, StripeView* v);
 
 }  // namespace plss

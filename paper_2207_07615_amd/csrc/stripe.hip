@@ -4,7 +4,7 @@
 // bound by the rate of scattered L2 requests, not by HBM.  The striped store
 // turns the gather into a stream: a workgroup owns a block of rows (a
 // "unit"), keeps the unit's row sums in LDS, and walks the columns in
-// stripes of kSW entries, staging each stripe's slice of x in LDS.  The
+// stripes of SW entries, staging each stripe's slice of x in LDS.  The
 // entries of a unit are grouped stripe by stripe and, inside a stripe, kept
 // in CSR order (row, then column); each entry packs its row inside the unit
 // and its column inside the stripe into one 32-bit word, so it still costs
@@ -156,14 +156,14 @@ __device__ __forceinline__ int upper_bound_i(const int* __restrict__ a, int lo, 
 // cnt[u * S + s] = entries of unit u whose column lies in stripe s.  The
 // source is a CSR direction whose column indices are offset by colbase.
 __global__ __launch_bounds__(kST) void k_st_count(const int* __restrict__ ptr, const int* __restrict__ idx,
-                                                  const int* __restrict__ urow, int S, int colbase,
+                                                  const int* __restrict__ urow, int S, int colbase, int sw,
                                                   int* __restrict__ cnt) {
   extern __shared__ int s_h[];
   const int u = blockIdx.x;
   for (int s = threadIdx.x; s < S; s += kST) s_h[s] = 0;
   __syncthreads();
   const int e0 = ptr[urow[u]], e1 = ptr[urow[u + 1]];
-  for (int e = e0 + threadIdx.x; e < e1; e += kST) atomicAdd(&s_h[(idx[e] - colbase) / kSW], 1);
+  for (int e = e0 + threadIdx.x; e < e1; e += kST) atomicAdd(&s_h[(idx[e] - colbase) / sw], 1);
   __syncthreads();
   for (int s = threadIdx.x; s < S; s += kST) cnt[(size_t)u * S + s] = s_h[s];
 }
@@ -177,7 +177,7 @@ __global__ __launch_bounds__(kST) void k_st_count(const int* __restrict__ ptr, c
 template <class Val>
 __global__ __launch_bounds__(kST) void k_st_scatter(const int* __restrict__ ptr, const int* __restrict__ idx,
                                                     const Val* __restrict__ val, const int* __restrict__ urow,
-                                                    const int* __restrict__ seg, int S, int colbase,
+                                                    const int* __restrict__ seg, int S, int colbase, int sw,
                                                     unsigned* __restrict__ opk, Val* __restrict__ oval) {
   extern __shared__ int s_cur[];  // S cursors
   __shared__ unsigned s_key[kST];
@@ -193,9 +193,9 @@ __global__ __launch_bounds__(kST) void k_st_scatter(const int* __restrict__ ptr,
     unsigned key = 0xFFFFFFFFu;
     if (e < e1) {
       const int col = idx[e] - colbase;
-      const int st = col / kSW;
+      const int st = col / sw;
       const int row = upper_bound_i(ptr, r0, r1 + 1, e) - 1;  // ptr[row] <= e < ptr[row + 1]
-      s_pk[t] = ((unsigned)(row - r0) << 16) | (unsigned)(col - st * kSW);
+      s_pk[t] = ((unsigned)(row - r0) << 16) | (unsigned)(col - st * sw);
       s_val[t] = val[e];
       key = ((unsigned)st << 10) | (unsigned)t;
     }
@@ -288,20 +288,42 @@ __global__ void k_st_interleave(const unsigned* __restrict__ pk, const Val* __re
 // ------------------------------------------------------------------ product
 
 // One lane-interleaved window of c entries into registers (the lane's
-// entries in CSR order).
+// entries in CSR order).  Float values: every lane loads all Qw =
+// ceil(c / 64) slots, so the loads depend on wave-uniform values only and
+// share one address; a lane without an entry in the last slot reads one of
+// the 63 entries past the window (the store has kStorePad entries of padding
+// past its end) and never uses it.  Double values: only the lane's own
+// slots are loaded (the uniform form needs more registers than the double
+// kernel has to spare, and measured 1-2 % slower there).
 template <class Val>
 __device__ __forceinline__ void load_window(const unsigned* __restrict__ pk, const Val* __restrict__ val, int base,
                                             int c, unsigned* pv, Val* vv) {
   const int lane = threadIdx.x & 63;
-  const int mine = c > 0 ? win_count(c, lane) : 0;
+  if constexpr (sizeof(Val) == 4) {
+    const int Qw = (c + 63) >> 6;
+    const unsigned* pp = pk + base + lane;
+    const Val* vp = val + base + lane;
 #pragma unroll
-  for (int q = 0; q < kQmax; ++q) {
-    if (q < mine) {
-      pv[q] = gload_nt(&pk[base + 64 * q + lane]);
-      vv[q] = gload_nt(&val[base + 64 * q + lane]);
-    } else {
-      pv[q] = 0xFFFFFFFFu;
-      vv[q] = Val(0);
+    for (int q = 0; q < kQmax; ++q) {
+      if (q < Qw) {
+        pv[q] = gload_nt(pp + 64 * q);
+        vv[q] = gload_nt(vp + 64 * q);
+      } else {
+        pv[q] = 0xFFFFFFFFu;
+        vv[q] = Val(0);
+      }
+    }
+  } else {
+    const int mine = c > 0 ? win_count(c, lane) : 0;
+#pragma unroll
+    for (int q = 0; q < kQmax; ++q) {
+      if (q < mine) {
+        pv[q] = gload_nt(&pk[base + 64 * q + lane]);
+        vv[q] = gload_nt(&val[base + 64 * q + lane]);
+      } else {
+        pv[q] = 0xFFFFFFFFu;
+        vv[q] = Val(0);
+      }
     }
   }
 }
@@ -309,7 +331,7 @@ __device__ __forceinline__ void load_window(const unsigned* __restrict__ pk, con
 // Row sums of one window [base, wend) of a wave range ending at we, added
 // to s_acc.  wc: open row sum carried in from the previous window, and out
 // to the next one.
-template <class Val, class Acc>
+template <int SW, class Val, class Acc>
 __device__ __forceinline__ void sum_window(const unsigned* __restrict__ pk, int base, int wend, int we,
                                            const unsigned* pv, const Val* vv, const Acc* __restrict__ xs,
                                            Acc* s_acc, Acc& wc) {
@@ -332,7 +354,7 @@ __device__ __forceinline__ void sum_window(const unsigned* __restrict__ pk, int 
   // entry reads a valid address and its product is never used
   Acc prods[kQmax];
 #pragma unroll
-  for (int q = 0; q < kQmax; ++q) prods[q] = Acc(vv[q]) * xs[pv[q] & (kSW - 1)];
+  for (int q = 0; q < kQmax; ++q) prods[q] = Acc(vv[q]) * xs[pv[q] & (SW - 1)];
 #pragma unroll
   for (int q = 0; q < kQmax; ++q) {
     if (q < mine) {
@@ -373,11 +395,11 @@ __device__ __forceinline__ void sum_window(const unsigned* __restrict__ pk, int 
 // unit list entry carries b << 24 | unit).  MODE_REFINE: r64 <- b - A x in
 // float64, partials of ||r64||^2 and ||b||^2.  MODE_PLAIN: r64 <- A p
 // (float64), or ypart[b] <- A_bᵀ p for a transposed store; no state.
-template <class Val, class Vin, class Acc, int MODE>
+template <class Val, class Vin, class Acc, int MODE, int SW, int RB>
 __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const int2* __restrict__ list,
                                                int transposed) {
-  __shared__ Acc s_x[2][kSW];
-  __shared__ Acc s_acc[kRBmax];
+  __shared__ Acc s_x[2][SW];
+  __shared__ Acc s_acc[RB];
   __shared__ double s_red[2][kSWaves];
 
   const int2 ent = list[blockIdx.x];
@@ -442,16 +464,16 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
   load_window(pk, val, wsB, min(64 * range_q(weB - wsB), weB - wsB), pB, vB);
 
   for (int i = threadIdx.x; i < nr; i += kST) s_acc[i] = Acc(0);
-  for (int j = threadIdx.x; j < kSW; j += kST) s_x[0][j] = j < xlen ? Acc(gload(&x[j])) : Acc(0);
+  for (int j = threadIdx.x; j < SW; j += kST) s_x[0][j] = j < xlen ? Acc(gload(&x[j])) : Acc(0);
   __syncthreads();
 
   auto stripe = [&](int s, int& ws0, int& we0, const unsigned* cpv, const Val* cvv, int ws2, int we2,
                     unsigned* mpv, Val* mvv) {
     // the next stripe's slice of x travels in registers during this stripe
-    Acc nx[kSW / kST];
+    Acc nx[SW / kST];
 #pragma unroll
-    for (int q = 0; q < kSW / kST; ++q) {
-      const int j = (s + 1) * kSW + q * kST + threadIdx.x;
+    for (int q = 0; q < SW / kST; ++q) {
+      const int j = (s + 1) * SW + q * kST + threadIdx.x;
       nx[q] = (s + 1 < S && j < xlen) ? Acc(gload(&x[j])) : Acc(0);
     }
     int ws3, we3;
@@ -462,17 +484,17 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
     if (we0 > ws0) {
       const int Q = range_q(we0 - ws0);
       Acc wc = Acc(0);  // open row sum carried from the previous window
-      sum_window<Val, Acc>(pk, ws0, min(ws0 + 64 * Q, we0), we0, cpv, cvv, xs, s_acc, wc);
+      sum_window<SW, Val, Acc>(pk, ws0, min(ws0 + 64 * Q, we0), we0, cpv, cvv, xs, s_acc, wc);
       for (int base = ws0 + 64 * Q; base < we0; base += 64 * Q) {
         const int wend = min(base + 64 * Q, we0);
         unsigned pv[kQmax];
         Val vv[kQmax];
         load_window(pk, val, base, wend - base, pv, vv);
-        sum_window<Val, Acc>(pk, base, wend, we0, pv, vv, xs, s_acc, wc);
+        sum_window<SW, Val, Acc>(pk, base, wend, we0, pv, vv, xs, s_acc, wc);
       }
     }
 #pragma unroll
-    for (int q = 0; q < kSW / kST; ++q) s_x[(s + 1) & 1][q * kST + threadIdx.x] = nx[q];
+    for (int q = 0; q < SW / kST; ++q) s_x[(s + 1) & 1][q * kST + threadIdx.x] = nx[q];
     ws0 = ws3;
     we0 = we3;
     __syncthreads();
@@ -546,23 +568,23 @@ static int st_grid(long long work, int per_block) {
   return (int)g;
 }
 
-void st_count(const int* ptr, const int* idx, int nunits, const int* d_urow, int S, int colbase, int* d_cnt,
+void st_count(const int* ptr, const int* idx, int nunits, const int* d_urow, int S, int colbase, int sw, int* d_cnt,
               hipStream_t s) {
   if (nunits <= 0 || S <= 0) return;
-  k_st_count<<<nunits, kST, sizeof(int) * (size_t)S, s>>>(ptr, idx, d_urow, S, colbase, d_cnt);
+  k_st_count<<<nunits, kST, sizeof(int) * (size_t)S, s>>>(ptr, idx, d_urow, S, colbase, sw, d_cnt);
   PLSS_HIP(hipGetLastError());
 }
 
 void st_scatter(const int* ptr, const int* idx, const void* val, bool f32, int nunits, const int* d_urow,
-                const int* d_seg, int S, int colbase, unsigned* opk, void* oval, hipStream_t s) {
+                const int* d_seg, int S, int colbase, int sw, unsigned* opk, void* oval, hipStream_t s) {
   if (nunits <= 0 || S <= 0) return;
   const size_t lds = sizeof(int) * (size_t)S;
   if (f32)
     k_st_scatter<float><<<nunits, kST, lds, s>>>(ptr, idx, static_cast<const float*>(val), d_urow, d_seg, S,
-                                                 colbase, opk, static_cast<float*>(oval));
+                                                 colbase, sw, opk, static_cast<float*>(oval));
   else
     k_st_scatter<double><<<nunits, kST, lds, s>>>(ptr, idx, static_cast<const double*>(val), d_urow, d_seg, S,
-                                                  colbase, opk, static_cast<double*>(oval));
+                                                  colbase, sw, opk, static_cast<double*>(oval));
   PLSS_HIP(hipGetLastError());
 }
 
@@ -592,19 +614,26 @@ void st_ysum(const double* ypart, int nblk, int n, double* y, hipStream_t s) {
 
 void launch_sspmv(int mode, bool f32, const Desc* d, const int2* list, int n, int transposed, hipStream_t s) {
   if (n <= 0) return;
+  constexpr int A1 = kSWA, A2 = kRBA, T1 = kSWT, T2 = kRBT;
   if (!f32) {
     switch (mode) {
-      case MODE_RESID: k_sspmv<double, double, double, MODE_RESID><<<n, kST, 0, s>>>(d, list, 0); break;
-      case MODE_TRANSB: k_sspmv<double, double, double, MODE_TRANSB><<<n, kST, 0, s>>>(d, list, 1); break;
-      case MODE_REFINE: k_sspmv<double, double, double, MODE_REFINE><<<n, kST, 0, s>>>(d, list, 0); break;
-      default: k_sspmv<double, double, double, MODE_PLAIN><<<n, kST, 0, s>>>(d, list, transposed); break;
+      case MODE_RESID: k_sspmv<double, double, double, MODE_RESID, A1, A2><<<n, kST, 0, s>>>(d, list, 0); break;
+      case MODE_TRANSB: k_sspmv<double, double, double, MODE_TRANSB, T1, T2><<<n, kST, 0, s>>>(d, list, 1); break;
+      case MODE_REFINE: k_sspmv<double, double, double, MODE_REFINE, A1, A2><<<n, kST, 0, s>>>(d, list, 0); break;
+      default:
+        if (transposed) k_sspmv<double, double, double, MODE_PLAIN, T1, T2><<<n, kST, 0, s>>>(d, list, 1);
+        else k_sspmv<double, double, double, MODE_PLAIN, A1, A2><<<n, kST, 0, s>>>(d, list, 0);
+        break;
     }
   } else {
     switch (mode) {
-      case MODE_RESID: k_sspmv<float, float, float, MODE_RESID><<<n, kST, 0, s>>>(d, list, 0); break;
-      case MODE_TRANSB: k_sspmv<float, float, float, MODE_TRANSB><<<n, kST, 0, s>>>(d, list, 1); break;
-      case MODE_REFINE: k_sspmv<float, double, double, MODE_REFINE><<<n, kST, 0, s>>>(d, list, 0); break;
-      default: k_sspmv<float, double, double, MODE_PLAIN><<<n, kST, 0, s>>>(d, list, transposed); break;
+      case MODE_RESID: k_sspmv<float, float, float, MODE_RESID, A1, A2><<<n, kST, 0, s>>>(d, list, 0); break;
+      case MODE_TRANSB: k_sspmv<float, float, float, MODE_TRANSB, T1, T2><<<n, kST, 0, s>>>(d, list, 1); break;
+      case MODE_REFINE: k_sspmv<float, double, double, MODE_REFINE, A1, A2><<<n, kST, 0, s>>>(d, list, 0); break;
+      default:
+        if (transposed) k_sspmv<float, double, double, MODE_PLAIN, T1, T2><<<n, kST, 0, s>>>(d, list, 1);
+        else k_sspmv<float, double, double, MODE_PLAIN, A1, A2><<<n, kST, 0, s>>>(d, list, 0);
+        break;
     }
   }
   PLSS_HIP(hipGetLastError());

@@ -42,12 +42,14 @@ def ragged(seed, m, n):
 
 
 CASES = {
-    # name: (matrix builder, unit_rows)
+    # name: (matrix builder, unit_rows); units above 8192 rows apply to the
+    # row-block stores of Aᵀ only (those of A hold at most 8192 rows)
     "ragged": (lambda: ragged(11, 9000, 13000), 37),
     "wide": (lambda: gen.tiny(4, 300, 20000, 30).A, 7),
     "dense_row": (lambda: gen.make_csr(gen.rng_for(9), 1, 9000, np.array([8000]), "normal"), 1),
     "zipf": (lambda: gen.large(m=60000, n=15000).A, 0),
     "one_unit": (lambda: gen.small(m=3000, n=1500).A, 8192),
+    "big_t_units": (lambda: gen.tiny(6, 2000, 40000, 40).A, 16384),
 }
 
 
@@ -62,7 +64,7 @@ def test_stripe_spmv_entrywise(h, case, storage):
     lay = M.layout(a_stripes=True, t_stripes=True, unit_rows=R)
     assert lay["a_stripes"] and lay["t_stripes"]
     if R:
-        assert lay["unit_rows"] == R
+        assert lay["unit_rows"] == min(R, 8192)
     S = A.astype(np.float32).scipy() if storage == "f32" else A.scipy()
     rng = np.random.default_rng(3)
     x = rng.standard_normal(A.n)
@@ -88,12 +90,15 @@ def test_stripe_layout_control(h):
     lay = M.layout(a_stripes=True, unit_rows=100)
     assert lay == {"a_stripes": True, "t_stripes": False, "unit_rows": 100}
     b1 = M.info()["device_bytes"]
+    # the store of A holds at most 8192 rows per unit
+    assert M.layout(a_stripes=True, unit_rows=12000)["unit_rows"] == 8192
+    M.layout(a_stripes=True, unit_rows=100)
     assert b1 >= b0 + A.nnz * 12
     lay = M.layout(t_stripes=True, unit_rows=100)
     assert lay["a_stripes"] and lay["t_stripes"]
     b2 = M.info()["device_bytes"]
     with pytest.raises(plss.PlssError):
-        M.layout(a_stripes=True, unit_rows=8193)
+        M.layout(a_stripes=True, unit_rows=16385)
     with pytest.raises(plss.PlssError):
         M.layout(a_stripes=True, unit_rows=-1)
     lay = M.layout(a_stripes=False, t_stripes=False)
@@ -107,7 +112,7 @@ def test_stripe_layout_control(h):
     assert np.all(abs(plss.spmv(h, M, x) - S @ x) <= 1e-14 * (abs(S) @ abs(x)))
 
 
-@pytest.mark.parametrize("R", [0, 64])
+@pytest.mark.parametrize("R", [0, 64, 16384])
 def test_stripe_solve_matches_oracle(h, R):
     """Zipf rows, 60000 x 15000: striped products in both directions."""
     say("stripe solve zipf", R)
