@@ -90,6 +90,13 @@ typedef struct {
                            P, AP are cleared (0: min(m, n, 256)) */
   int32_t chunk;        /* iterations per launch batch between host checks (0: auto) */
   int32_t timing;       /* record per-kernel device times (see plss_kernel_times) */
+  int32_t engine;       /* residual sketch: 0 = automatic, 1 = one launch per phase
+                           (all CUs on the system), 2 = single workgroup: the whole
+                           solve in one workgroup, vectors and row pointers in
+                           LDS (requires 8n + (m + 2n) x vector bytes +
+                           4 (m + n) <= 156 KiB, about m + 3.5 n <= 19,900 in
+                           float64; automatic for those systems with at most 2^18
+                           entries) */
 } plss_opts;
 
 typedef struct {

@@ -25,7 +25,7 @@ class plss_opts(C.Structure):
                 ("tol_absolute", C.c_int32), ("refine", C.c_int32), ("inner_tol", C.c_double),
                 ("max_outer", C.c_int64), ("x0", C.c_void_p), ("wi_diag", C.c_void_p),
                 ("row_perm", C.c_void_p), ("hist_cap", C.c_int64), ("chunk", C.c_int32),
-                ("timing", C.c_int32)]
+                ("timing", C.c_int32), ("engine", C.c_int32)]
 
 
 class plss_info(C.Structure):
@@ -35,6 +35,9 @@ class plss_info(C.Structure):
 
 class plss_layout(C.Structure):
     _fields_ = [("a_stripes", C.c_int32), ("t_stripes", C.c_int32), ("unit_rows", C.c_int32)]
+
+
+ENGINE = {"auto": 0, "multi": 1, "single": 2}
 
 
 EXPORTS = {

@@ -25,6 +25,7 @@ SOURCES = [
     "sketch_kernels.hip",
     "multi_kernels.hip",
     "stripe.hip",
+    "small.hip",
     "runtime.cpp",
     "solve.cpp",
     "ops.cpp",

@@ -48,6 +48,8 @@ constexpr int kSWA = 4096, kRBA = 8192;
 constexpr int kSWT = 2048, kRBT = 16384;
 constexpr int kSThreads = 1024;
 constexpr int kMaxStripes = 8192;  // stripes per store (cursor table of the builder in LDS)
+constexpr size_t kSmallLds = 156 * 1024;  // LDS for r, p, y of a single-workgroup solve
+constexpr long long kSmallNnz = 1 << 18;  // automatic single-workgroup solves up to this many entries
 constexpr int kStorePad = 64;      // entries allocated past the end of a striped store: a
                                    // window's last slot is loaded by every lane of the wave
 
@@ -113,6 +115,10 @@ struct Desc {
   int t_nwt;
   int t_ntiles;
   int m, n;
+  // rows of more than 64 entries of the CSR and the CSC (single-workgroup solve)
+  const int* a_long;
+  const int* t_long;
+  int a_nlong, t_nlong;
   int u_nblk;                  // blocks of the vector-update kernel
   // row-blocked CSC: block b holds the entries of rows [rb[b], rb[b+1])
   int nblk;                    // 1: products with Aᵀ use the CSC above

@@ -63,3 +63,9 @@ void launch_sspmv(int mode, bool f32, const Desc* d, const int2* list, int n, in
 // exclusive scan of n counts into out[0..n] (work: (n + 1023) / 1024 + 1 long longs)
 void scan_counts(const int* cnt, int n, int* out, void* work, hipStream_t s);
 }  // namespace plss
+
+namespace plss {
+// single-workgroup solve (small.hip): one workgroup per system in `sys`
+bool small_fits(int m, int n, bool f32);
+void launch_small(bool f32, const Desc* d, const int* sys, int n, hipStream_t s);
+}  // namespace plss

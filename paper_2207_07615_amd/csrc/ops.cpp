@@ -1,5 +1,6 @@
 // Plain products with A / Aᵀ, input checks and the tile-width autotuner.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -108,29 +109,47 @@ void spmv_plain(const plss_matrix* A, bool transpose, const double* x, double* y
   PLSS_HIP(hipStreamSynchronize(s));
 }
 
+// Arrays the host can read directly (plain or pinned host memory).
+static bool host_readable(const void* p) {
+  hipPointerAttribute_t a;
+  if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return true;  // not known to HIP: ordinary host memory
+  }
+  return a.type == hipMemoryTypeUnregistered || a.type == hipMemoryTypeHost;
+}
+
+// b, x0 finite; wi_diag finite and positive.  Host arrays are checked on the
+// host (no device round trip for small solves), device arrays on the device.
 void check_finite_inputs(const plss_matrix* A, const double* b, const plss_opts* o, hipStream_t s) {
-  Scratch sc;
-  const size_t nmax = std::max(A->m, A->n);
-  double* tmp = static_cast<double*>(sc.get(8 * nmax));
-  int* flag = static_cast<int*>(sc.get(sizeof(int) * 4));
-  PLSS_HIP(hipMemsetAsync(flag, 0, sizeof(int) * 4, s));
   struct C {
     const double* p;
     size_t n;
     int pos;
-    int slot;
-  } cs[3] = {{b, (size_t)A->m, 0, 0}, {o->x0, (size_t)A->n, 0, 1}, {o->wi_diag, (size_t)A->n, 1, 2}};
+    const char* msg;
+  } cs[3] = {{b, (size_t)A->m, 0, "b has a non-finite entry"},
+             {o->x0, (size_t)A->n, 0, "x0 has a non-finite entry"},
+             {o->wi_diag, (size_t)A->n, 1, "wi_diag must be finite and positive"}};
   for (auto& c : cs) {
     if (!c.p) continue;
+    if (host_readable(c.p)) {
+      for (size_t i = 0; i < c.n; ++i) {
+        const double v = c.p[i];
+        if (!std::isfinite(v) || (c.pos && !(v > 0.0))) throw InvalidArg{c.msg};
+      }
+      continue;
+    }
+    Scratch sc;
+    double* tmp = static_cast<double*>(sc.get(8 * c.n));
+    int* flag = static_cast<int*>(sc.get(sizeof(int)));
+    PLSS_HIP(hipMemsetAsync(flag, 0, sizeof(int), s));
     PLSS_HIP(hipMemcpyAsync(tmp, c.p, 8 * c.n, hipMemcpyDefault, s));
-    launch_check(tmp, (long long)c.n, c.pos, flag + c.slot, s);
+    launch_check(tmp, (long long)c.n, c.pos, flag, s);
+    int hf = 0;
+    PLSS_HIP(hipMemcpyAsync(&hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    PLSS_HIP(hipStreamSynchronize(s));
+    if (hf) throw InvalidArg{c.msg};
   }
-  int hf[4] = {0, 0, 0, 0};
-  PLSS_HIP(hipMemcpyAsync(hf, flag, sizeof(hf), hipMemcpyDeviceToHost, s));
-  PLSS_HIP(hipStreamSynchronize(s));
-  if (hf[0]) throw InvalidArg{"b has a non-finite entry"};
-  if (hf[1]) throw InvalidArg{"x0 has a non-finite entry"};
-  if (hf[2]) throw InvalidArg{"wi_diag must be finite and positive"};
 }
 
 // Time the plain product for each tile width and keep the fastest.

@@ -87,6 +87,19 @@ void set_tiles(PlssDir& d, int V, hipStream_t s) {
   d.V = V;
 }
 
+void set_long_rows(PlssDir& d, hipStream_t s) {
+  std::vector<int> l;
+  for (int i = 0; i < d.nrows; ++i)
+    if (d.h_ptr[i + 1] - d.h_ptr[i] > 64) l.push_back(i);
+  dfree(d.lrows);
+  d.lrows = static_cast<int*>(dmalloc(sizeof(int) * std::max<size_t>(1, l.size())));
+  if (!l.empty()) {
+    PLSS_HIP(hipMemcpyAsync(d.lrows, l.data(), sizeof(int) * l.size(), hipMemcpyHostToDevice, s));
+    PLSS_HIP(hipStreamSynchronize(s));
+  }
+  d.nlong = (int)l.size();
+}
+
 size_t matrix_footprint(long long m, long long n, long long nnz, bool f32) {
   const size_t v = f32 ? 4 : 8;
   const bool blocked = (size_t)m * v > (3u << 20) && nnz >= 8 * 64;
@@ -351,6 +364,8 @@ plss_matrix* matrix_create(plss_handle* h, const plss_csr* A, plss_dtype storage
     PLSS_HIP(hipStreamSynchronize(s));
     set_tiles(a, 8, s);
     set_tiles(t, 8, s);
+    set_long_rows(a, s);
+    set_long_rows(t, s);
     build_row_blocks(M, s);
   } catch (...) {
     if (d_v64 && d_v64 != M->A.val) dfree(d_v64);
@@ -387,6 +402,7 @@ void matrix_destroy(plss_matrix* M) {
     dfree(d->val);
     dfree(d->tile);
     dfree(d->grp);
+    dfree(d->lrows);
   }
   for (int b = 0; b < kMaxBlk; ++b) {
     PlssDir& d = M->TB[b];
@@ -464,6 +480,7 @@ void handle_release(plss_handle* h) {
   const int left = --h->refs;
   if (h->closed && left <= 0) {
     (void)hipStreamSynchronize(h->stream);
+    workspace_free(h->ws);
     (void)hipStreamDestroy(h->stream);
     delete h;
   }

@@ -20,6 +20,8 @@ struct PlssDir {
   int nwt = 0;           // wave tiles
   int ntiles = 0;        // groups of 4 wave tiles (workgroups per launch)
   int V = 8;             // entries per lane of a wave tile (64*V entries)
+  int* lrows = nullptr;  // rows of more than 64 entries (single-workgroup solve)
+  int nlong = 0;
   std::vector<int> h_ptr;  // host copy of ptr (tile construction)
 };
 
@@ -36,6 +38,11 @@ struct PlssStripes {
   size_t bytes = 0;
 };
 
+namespace plss {
+struct Workspace;
+void workspace_free(Workspace* w);
+}  // namespace plss
+
 struct plss_handle {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -46,6 +53,7 @@ struct plss_handle {
   bool closed = false;
   double kt_ms[4] = {0, 0, 0, 0};
   long long kt_n[4] = {0, 0, 0, 0};
+  plss::Workspace* ws = nullptr;  // scratch of the calls on this handle (solve.cpp)
 };
 
 struct plss_matrix {
@@ -77,6 +85,7 @@ void dfree(void* p);
 std::vector<int> make_tiles(const std::vector<int>& ptr, int V);
 std::vector<int> make_groups(const std::vector<int>& ptr, const std::vector<int>& tiles, int V);
 void set_tiles(PlssDir& d, int V, hipStream_t s);
+void set_long_rows(PlssDir& d, hipStream_t s);
 
 // validated store creation (throws InvalidArg / OutOfMemory / DeviceError)
 plss_matrix* matrix_create(plss_handle* h, const plss_csr* A, plss_dtype storage, hipStream_t s);

@@ -80,6 +80,8 @@ struct plss_server {
   std::vector<plss::Desc> h_desc;
   std::vector<int> free_slots;
   plss::ListSet lists;
+  int* d_small_ids = nullptr;  // slots of the small systems launched this pass
+  int* h_small_ids = nullptr;  // pinned staging of the same
 };
 
 namespace plss {
@@ -109,10 +111,28 @@ void host_validate(const Req& r) {
     if (!std::isfinite(v)) throw InvalidArg{"b has a non-finite entry"};
 }
 
+// Launch lists of the admitted systems that run on the per-phase engine
+// (small systems run whole in one workgroup and are not stepped by chunks).
 void rebuild_lists(plss_server* S) {
   std::vector<std::pair<int, const SysRun*>> items;
-  for (Req* r : S->active) items.push_back({r->slot, r->run.get()});
+  for (Req* r : S->active)
+    if (!r->run->small) items.push_back({r->slot, r->run.get()});
   S->lists.build(items, S->main);
+}
+
+// One persistent launch (per storage type) for the small systems that joined:
+// each workgroup runs its system to the end, ahead of this pass's chunk.
+void launch_joined_small(plss_server* S, const std::vector<Req*>& joined) {
+  std::vector<int> s64, s32;
+  for (Req* r : joined)
+    if (r->run->small) (r->run->f32 ? s32 : s64).push_back(r->slot);
+  if (s64.empty() && s32.empty()) return;
+  int k = 0;
+  for (int v : s64) S->h_small_ids[k++] = v;
+  for (int v : s32) S->h_small_ids[k++] = v;
+  PLSS_HIP(hipMemcpyAsync(S->d_small_ids, S->h_small_ids, sizeof(int) * k, hipMemcpyHostToDevice, S->main));
+  launch_small(false, S->d_desc, S->d_small_ids, (int)s64.size(), S->main);
+  launch_small(true, S->d_desc, S->d_small_ids + s64.size(), (int)s32.size(), S->main);
 }
 
 // Upload and prepare one request on the side stream (server thread).
@@ -219,7 +239,8 @@ void loop(plss_server* S) {
         r->state = RQ_ACTIVE;
         S->active.push_back(r);
       }
-      joining.clear();
+      std::vector<Req*> joined;
+      joined.swap(joining);
       std::vector<Req*> keep;
       for (Req* r : S->active) {
         if (r->cancel) {
@@ -237,15 +258,21 @@ void loop(plss_server* S) {
       S->active.swap(keep);
       if (S->active.empty()) continue;
       if (changed) rebuild_lists(S);
-      // one chunk for every admitted system
-      const int chunk = 16;
-      const int outer_every = S->lists.any_f32 ? 4 : chunk;
-      S->lists.outer_seq(S->d_desc, S->main);
-      for (int it = 0; it < chunk; ++it) {
-        if (it > 0 && it % outer_every == 0) S->lists.outer_seq(S->d_desc, S->main);
-        S->lists.iteration(S->d_desc, S->main, nullptr);
+      std::vector<Req*> joined_live;
+      for (Req* r : joined)
+        if (r->state == RQ_ACTIVE) joined_live.push_back(r);
+      launch_joined_small(S, joined_live);
+      // one chunk for every admitted system on the per-phase engine
+      if (S->lists.nsys > 0) {
+        const int chunk = 16;
+        const int outer_every = S->lists.any_f32 ? 4 : chunk;
+        S->lists.outer_seq(S->d_desc, S->main);
+        for (int it = 0; it < chunk; ++it) {
+          if (it > 0 && it % outer_every == 0) S->lists.outer_seq(S->d_desc, S->main);
+          S->lists.iteration(S->d_desc, S->main, nullptr);
+        }
+        S->lists.outer_seq(S->d_desc, S->main);
       }
-      S->lists.outer_seq(S->d_desc, S->main);
       PLSS_HIP(hipMemcpyAsync(S->h_slots, S->d_slots, sizeof(State) * S->max_slots, hipMemcpyDeviceToHost, S->main));
       // overlap: admit while the chunk runs
       more = admit(S);
@@ -321,9 +348,19 @@ plss_server* server_create(plss_handle* h, size_t budget, int max_slots) {
     PLSS_HIP(hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking));
     S->d_slots = static_cast<State*>(dmalloc(sizeof(State) * max_slots));
     S->d_desc = static_cast<Desc*>(dmalloc(sizeof(Desc) * max_slots));
+    S->d_small_ids = static_cast<int*>(dmalloc(sizeof(int) * max_slots));
+    PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&S->h_small_ids), sizeof(int) * max_slots, hipHostMallocDefault));
     PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&S->h_slots), sizeof(State) * max_slots, hipHostMallocDefault));
     std::memset(S->h_slots, 0, sizeof(State) * max_slots);
   } catch (...) {
+    dfree(S->d_slots);
+    dfree(S->d_desc);
+    dfree(S->d_small_ids);
+    if (S->h_slots) (void)hipHostFree(S->h_slots);
+    if (S->h_small_ids) (void)hipHostFree(S->h_small_ids);
+    if (S->main) (void)hipStreamDestroy(S->main);
+    if (S->side) (void)hipStreamDestroy(S->side);
+    delete S;
     (void)hipSetDevice(prev);
     throw;
   }
@@ -440,7 +477,9 @@ void server_destroy(plss_server* S) {
   }
   dfree(S->d_slots);
   dfree(S->d_desc);
+  dfree(S->d_small_ids);
   if (S->h_slots) (void)hipHostFree(S->h_slots);
+  if (S->h_small_ids) (void)hipHostFree(S->h_small_ids);
   (void)hipStreamDestroy(S->main);
   (void)hipStreamDestroy(S->side);
   plss_handle* h = S->h;

@@ -26,37 +26,79 @@ void validate_opts(const plss_opts* o, bool f32) {
     throw InvalidArg{"inner_tol must be in (0, 1)"};
   if (f32 && o->refine && o->max_outer <= 0) throw InvalidArg{"max_outer must be positive"};
   if (o->chunk < 0) throw InvalidArg{"chunk must be >= 0"};
+  if (o->engine < 0 || o->engine > 2) throw InvalidArg{"engine must be 0, 1 or 2"};
 }
 
-SysRun::~SysRun() { dfree(arena); }
+SysRun::~SysRun() {
+  if (own_arena) dfree(arena);
+}
 
-void SysRun::setup(const plss_matrix* M, const double* b_in, const plss_opts* o, long long hist_len_in,
-                   State* d_state, Desc* desc_slot_unused) {
-  (void)desc_slot_unused;
-  A = M;
-  f32 = M->f32;
+namespace {
+// Offsets of the per-system vectors and partials inside one arena.
+struct Layout {
+  size_t o_b, o_xo, o_x, o_r64, o_r, o_p, o_y, o_c, o_wi, o_pr, o_pb, o_pp, o_pt, o_yp, o_h, total;
+  int rho_cnt;
+};
+Layout plan(const plss_matrix* M, const plss_opts* o, long long hist_len, bool use_stripes) {
+  const bool f32 = M->f32;
   const size_t m = M->m, n = M->n;
   const size_t vs = f32 ? 4 : 8;
-  u_nblk = (int)((n + 1023) / 1024);
-  hist_len = std::max<long long>(1, hist_len_in);
-  // arena layout
+  const int u_nblk = (int)((n + 1023) / 1024);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o2 = off;
     off = align_up(off + bytes);
     return o2;
   };
-  const size_t o_b = take(8 * m), o_xo = take(8 * n), o_x = f32 ? take(8 * n) : 0, o_r64 = take(8 * m);
-  const size_t o_r = take(vs * m), o_p = take(vs * n), o_y = take(vs * n), o_c = f32 ? take(vs * m) : 0;
-  const size_t o_wi = o->wi_diag ? take(8 * n) : 0;
+  Layout L{};
+  L.o_b = take(8 * m);
+  L.o_xo = take(8 * n);
+  L.o_x = f32 ? take(8 * n) : 0;
+  L.o_r64 = take(8 * m);
+  L.o_r = take(vs * m);
+  L.o_p = take(vs * n);
+  L.o_y = take(vs * n);
+  L.o_c = f32 ? take(vs * m) : 0;
+  L.o_wi = o->wi_diag ? take(8 * n) : 0;
+  const bool as = use_stripes && M->a_striped;
+  L.rho_cnt = as ? M->SA.nunits : M->A.ntiles;
+  L.o_pr = take(8 * (size_t)L.rho_cnt);
+  L.o_pb = take(8 * (size_t)L.rho_cnt);
+  L.o_pp = take(8 * (size_t)std::max(M->T.ntiles, u_nblk));
+  L.o_pt = take(8 * (size_t)u_nblk);
+  L.o_yp = M->nblk > 1 ? take(vs * n * M->nblk) : 0;
+  L.o_h = take(8 * (size_t)std::max<long long>(1, hist_len));
+  L.total = off;
+  return L;
+}
+}  // namespace
+
+size_t SysRun::arena_bytes(const plss_matrix* M, const plss_opts* o, long long hist_len, bool use_stripes) {
+  return plan(M, o, hist_len, use_stripes).total;
+}
+
+void SysRun::setup(const plss_matrix* M, const double* b_in, const plss_opts* o, long long hist_len_in,
+                   State* d_state, char* mem) {
+  (void)b_in;
+  A = M;
+  f32 = M->f32;
+  const size_t m = M->m, n = M->n;
+  u_nblk = (int)((n + 1023) / 1024);
+  hist_len = std::max<long long>(1, hist_len_in);
+  const Layout L = plan(M, o, hist_len, use_stripes);
+  const size_t o_b = L.o_b, o_xo = L.o_xo, o_x = L.o_x, o_r64 = L.o_r64, o_r = L.o_r, o_p = L.o_p, o_y = L.o_y,
+               o_c = L.o_c, o_wi = L.o_wi, o_pr = L.o_pr, o_pb = L.o_pb, o_pp = L.o_pp, o_pt = L.o_pt,
+               o_yp = L.o_yp, o_h = L.o_h;
   const bool as = use_stripes && M->a_striped, ts = use_stripes && M->t_striped;
-  const int rho_cnt = as ? M->SA.nunits : M->A.ntiles;
-  const size_t o_pr = take(8 * (size_t)rho_cnt), o_pb = take(8 * (size_t)rho_cnt);
-  const size_t o_pp = take(8 * (size_t)std::max(M->T.ntiles, u_nblk)), o_pt = take(8 * u_nblk);
-  const size_t o_yp = M->nblk > 1 ? take(vs * n * M->nblk) : 0;
-  const size_t o_h = take(8 * (size_t)hist_len);
-  arena = static_cast<char*>(dmalloc(off));
-  bytes = off;
+  const int rho_cnt = L.rho_cnt;
+  if (mem) {
+    arena = mem;
+    own_arena = false;
+  } else {
+    arena = static_cast<char*>(dmalloc(L.total));
+    own_arena = true;
+  }
+  bytes = L.total;
   std::memset(&desc, 0, sizeof(desc));
   desc.a_ptr = M->A.ptr;
   desc.a_idx = M->A.idx;
@@ -74,6 +116,10 @@ void SysRun::setup(const plss_matrix* M, const double* b_in, const plss_opts* o,
   desc.t_grp = M->T.grp;
   desc.m = (int)m;
   desc.n = (int)n;
+  desc.a_long = M->A.lrows;
+  desc.t_long = M->T.lrows;
+  desc.a_nlong = M->A.nlong;
+  desc.t_nlong = M->T.nlong;
   desc.u_nblk = u_nblk;
   desc.nblk = M->nblk;
   for (int b = 0; b < M->nblk && M->nblk > 1; ++b) {
@@ -109,6 +155,13 @@ void SysRun::setup(const plss_matrix* M, const double* b_in, const plss_opts* o,
   desc.st = d_state;
   desc.is_f32 = f32;
 
+  // single-workgroup engine: residual sketch, vectors in LDS; automatic up
+  // to kSmallNnz entries, where launches and host polls cost more than the work
+  const bool fits = o->sketch == PLSS_SKETCH_RESIDUAL && small_fits((int)m, (int)n, f32);
+  if (o->engine == 2 && !fits)
+    throw InvalidArg{"engine 2 needs the residual sketch and vectors and row pointers within 156 KiB of LDS"};
+  small = o->engine == 2 || (o->engine == 0 && fits && M->nnz <= kSmallNnz);
+
   std::memset(&st0, 0, sizeof(st0));
   st0.done = 1;  // the outer step runs first: r64 = b - A x0, then the inner start
   st0.final_done = 0;
@@ -133,14 +186,53 @@ void SysRun::upload(const double* b_in, const double* x0, const double* wi, hipS
 
 // ------------------------------------------------------------------ batch runner
 
-BatchRunner::BatchRunner(plss_handle* h) : h_(h) {}
-
-BatchRunner::~BatchRunner() {
-  dfree(d_desc_);
-  dfree(d_state_);
-  if (h_state_) (void)hipHostFree(h_state_);
-  for (auto e : events_) (void)hipEventDestroy(e);
+char* Workspace::dev_block(size_t bytes) {
+  if (bytes > dev_cap) {
+    dfree(dev);
+    dev = nullptr;
+    dev_cap = 0;
+    const size_t want = std::max(bytes, dev_cap + dev_cap / 2);
+    dev = static_cast<char*>(dmalloc(want));
+    dev_cap = want;
+  }
+  return dev;
 }
+
+char* Workspace::pin_block(size_t bytes) {
+  if (bytes > pin_cap) {
+    if (pin) (void)hipHostFree(pin);
+    pin = nullptr;
+    pin_cap = 0;
+    const size_t want = std::max<size_t>(bytes, 4096);
+    PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&pin), want, hipHostMallocDefault));
+    pin_cap = want;
+  }
+  return pin;
+}
+
+Workspace::~Workspace() {
+  dfree(dev);
+  if (pin) (void)hipHostFree(pin);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  for (auto e : iter_events) (void)hipEventDestroy(e);
+}
+
+Workspace& workspace(plss_handle* h) {
+  if (!h->ws) {
+    std::unique_ptr<Workspace> w(new Workspace());
+    PLSS_HIP(hipEventCreate(&w->t0));
+    PLSS_HIP(hipEventCreate(&w->t1));
+    h->ws = w.release();
+  }
+  return *h->ws;
+}
+
+void workspace_free(Workspace* w) { delete w; }
+
+BatchRunner::BatchRunner(plss_handle* h) : h_(h), ws_(workspace(h)) {}
+
+BatchRunner::~BatchRunner() = default;
 
 // ------------------------------------------------------------------ launch lists
 
@@ -276,38 +368,77 @@ void BatchRunner::add(const plss_matrix* A, const double* b, const plss_opts* o,
 
 void BatchRunner::prepare(hipStream_t s) {
   const int ns = (int)items_.size();
-  d_state_ = static_cast<State*>(dmalloc(sizeof(State) * ns));
-  d_desc_ = static_cast<Desc*>(dmalloc(sizeof(Desc) * ns));
-  PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_state_), sizeof(State) * ns, hipHostMallocDefault));
+  // one device block from the handle's workspace: states, descriptors, the
+  // single-workgroup system list, then every system's arena
+  const size_t o_state = 0;
+  const size_t o_desc = align_up(o_state + sizeof(State) * ns);
+  const size_t o_small = align_up(o_desc + sizeof(Desc) * ns);
+  size_t off = align_up(o_small + sizeof(int) * ns);
+  std::vector<size_t> o_arena(ns);
+  for (int i = 0; i < ns; ++i) {
+    o_arena[i] = off;
+    off = align_up(off + SysRun::arena_bytes(items_[i].A, &items_[i].o, std::max<long long>(1, items_[i].hist_len),
+                                             true));
+  }
+  char* dev = ws_.dev_block(off);
+  // pinned: states, descriptors, single-workgroup system list (sized once here,
+  // so the block does not move while copies from it are pending)
+  char* pin = ws_.pin_block(sizeof(State) * ns + sizeof(Desc) * ns + sizeof(int) * ns);
+  d_state_ = reinterpret_cast<State*>(dev + o_state);
+  d_desc_ = reinterpret_cast<Desc*>(dev + o_desc);
+  d_small_ = reinterpret_cast<int*>(dev + o_small);
+  h_state_ = reinterpret_cast<State*>(pin);
+  Desc* h_desc = reinterpret_cast<Desc*>(pin + sizeof(State) * ns);
+  h_small_ = reinterpret_cast<int*>(pin + sizeof(State) * ns + sizeof(Desc) * ns);
   runs_.resize(ns);
-  std::vector<Desc> descs(ns);
-  std::vector<State> st(ns);
   for (int i = 0; i < ns; ++i) {
     Item& it = items_[i];
     runs_[i].reset(new SysRun());
     SysRun& r = *runs_[i];
-    r.setup(it.A, it.b, &it.o, it.hist_len, d_state_ + i, nullptr);
+    r.setup(it.A, it.b, &it.o, it.hist_len, d_state_ + i, dev + o_arena[i]);
     r.upload(it.b, it.o.x0, it.o.wi_diag, s);
-    descs[i] = r.desc;
-    st[i] = r.st0;
+    h_desc[i] = r.desc;
+    h_state_[i] = r.st0;
   }
-  PLSS_HIP(hipMemcpyAsync(d_desc_, descs.data(), sizeof(Desc) * ns, hipMemcpyHostToDevice, s));
-  PLSS_HIP(hipMemcpyAsync(d_state_, st.data(), sizeof(State) * ns, hipMemcpyHostToDevice, s));
-  // finite check of b (and x0 / wi) on the device
-  PLSS_HIP(hipStreamSynchronize(s));
-  std::memcpy(h_state_, st.data(), sizeof(State) * ns);
+  PLSS_HIP(hipMemcpyAsync(d_desc_, h_desc, sizeof(Desc) * ns, hipMemcpyHostToDevice, s));
+  PLSS_HIP(hipMemcpyAsync(d_state_, h_state_, sizeof(State) * ns, hipMemcpyHostToDevice, s));
 }
 
 void BatchRunner::build_lists(const std::vector<int>& active, hipStream_t s) {
   std::vector<std::pair<int, const SysRun*>> items;
   for (int i : active) items.push_back({i, runs_[i].get()});
-  lists_.build(items, s);
+  ws_.lists.build(items, s);
 }
 
 void BatchRunner::run(hipStream_t s, bool timing, int chunk_req) {
   const int ns = (int)items_.size();
-  std::vector<int> active;
-  for (int i = 0; i < ns; ++i) active.push_back(i);
+  std::vector<int> active, small64, small32;
+  for (int i = 0; i < ns; ++i) {
+    if (!runs_[i]->small) active.push_back(i);
+    else (runs_[i]->f32 ? small32 : small64).push_back(i);
+  }
+  hipEvent_t t0 = ws_.t0, t1 = ws_.t1;
+  if (!small64.empty() || !small32.empty()) {
+    // one persistent launch per storage type; each workgroup solves its system
+    int k = 0;
+    for (int i : small64) h_small_[k++] = i;
+    for (int i : small32) h_small_[k++] = i;
+    PLSS_HIP(hipMemcpyAsync(d_small_, h_small_, sizeof(int) * k, hipMemcpyHostToDevice, s));
+    PLSS_HIP(hipEventRecord(t0, s));
+    launch_small(false, d_desc_, d_small_, (int)small64.size(), s);
+    launch_small(true, d_desc_, d_small_ + small64.size(), (int)small32.size(), s);
+  } else {
+    PLSS_HIP(hipEventRecord(t0, s));
+  }
+  if (active.empty()) {
+    PLSS_HIP(hipMemcpyAsync(h_state_, d_state_, sizeof(State) * ns, hipMemcpyDeviceToHost, s));
+    PLSS_HIP(hipEventRecord(t1, s));
+    PLSS_HIP(hipEventSynchronize(t1));
+    float ms = 0;
+    PLSS_HIP(hipEventElapsedTime(&ms, t0, t1));
+    elapsed_ms_ = ms;
+    return;
+  }
   build_lists(active, s);
   bool any_f32 = false;
   double bytes_iter = 0;
@@ -322,14 +453,12 @@ void BatchRunner::run(hipStream_t s, bool timing, int chunk_req) {
   int cmax = (int)std::min(128.0, std::max(8.0, 4e-3 / t_iter));
   int chunk = chunk_req > 0 ? chunk_req : std::min(16, cmax);
   const int outer_every = any_f32 ? 4 : 1 << 30;
+  std::vector<hipEvent_t>& events_ = ws_.iter_events;
   if (timing && events_.empty()) {
     events_.resize(5 * 128);
     for (auto& e : events_) PLSS_HIP(hipEventCreate(&e));
   }
-  hipEvent_t t0, t1;
-  PLSS_HIP(hipEventCreate(&t0));
-  PLSS_HIP(hipEventCreate(&t1));
-  PLSS_HIP(hipEventRecord(t0, s));
+  const ListSet& lists_ = ws_.lists;
   while (!active.empty()) {
     lists_.outer_seq(d_desc_, s);
     const int c = timing ? std::min(chunk, 128) : chunk;
@@ -364,8 +493,6 @@ void BatchRunner::run(hipStream_t s, bool timing, int chunk_req) {
   float ms = 0;
   PLSS_HIP(hipEventElapsedTime(&ms, t0, t1));
   elapsed_ms_ = ms;
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
 }
 
 void BatchRunner::result(int i, double* x, double* hist, long long hist_cap, plss_info* info,

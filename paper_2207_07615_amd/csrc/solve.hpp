@@ -17,13 +17,18 @@ struct SysRun {
   Desc desc{};
   State st0{};
   char* arena = nullptr;
+  bool own_arena = false;
   size_t bytes = 0;
   long long hist_len = 0;
   int u_nblk = 0;
   bool use_stripes = true;  // the residual path may use the matrix's striped stores
+  bool small = false;       // solved by one workgroup (single-workgroup engine)
   ~SysRun();
+  // device bytes of the arena setup() lays out
+  static size_t arena_bytes(const plss_matrix* M, const plss_opts* o, long long hist_len, bool use_stripes);
+  // mem: arena_bytes() of device memory owned by the caller, or null (own allocation)
   void setup(const plss_matrix* M, const double* b, const plss_opts* o, long long hist_len,
-             State* d_state, Desc* unused);
+             State* d_state, char* mem);
   void upload(const double* b, const double* x0, const double* wi, hipStream_t s);
 };
 
@@ -52,6 +57,23 @@ struct ListSet {
   void iteration(const Desc* dd, hipStream_t s, hipEvent_t* ev) const;
 };
 
+// Scratch reused by the calls on one handle (they are serialised by the
+// handle's mutex and synchronise before returning): one device block and
+// one pinned host block that only grow, the launch lists and events.
+struct Workspace {
+  char* dev = nullptr;
+  size_t dev_cap = 0;
+  char* pin = nullptr;
+  size_t pin_cap = 0;
+  ListSet lists;
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  std::vector<hipEvent_t> iter_events;  // 5 per timed iteration
+  char* dev_block(size_t bytes);
+  char* pin_block(size_t bytes);
+  ~Workspace();
+};
+Workspace& workspace(plss_handle* h);
+
 class BatchRunner {
  public:
   explicit BatchRunner(plss_handle* h);
@@ -73,13 +95,14 @@ class BatchRunner {
   void build_lists(const std::vector<int>& active, hipStream_t s);
 
   plss_handle* h_;
+  Workspace& ws_;
   std::vector<Item> items_;
   std::vector<std::unique_ptr<SysRun>> runs_;
   Desc* d_desc_ = nullptr;
   State* d_state_ = nullptr;
+  int* d_small_ = nullptr;  // systems of the single-workgroup engine (float64 first, then float32)
   State* h_state_ = nullptr;
-  ListSet lists_;
-  std::vector<hipEvent_t> events_;
+  int* h_small_ = nullptr;
   float elapsed_ms_ = 0;
 };
 

@@ -26,6 +26,7 @@
 // ahead, so their memory latency overlaps the arithmetic of the stripes in
 // between.
 #include "kernels.hpp"
+#include "wave.hpp"
 
 namespace plss {
 
@@ -40,37 +41,6 @@ __device__ __forceinline__ T swsum(T v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
-}
-
-// DPP controls of GFX9-family wave64 cross-lane moves
-constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
-constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kWaveShl1 = 0x130, kWaveShr1 = 0x138;
-
-// v from another lane per the DPP control; lanes without a source (or outside
-// row_mask) read 0
-template <int CTRL, int RM, bool BC>
-__device__ __forceinline__ int dpp32(int v) {
-  return __builtin_amdgcn_update_dpp(0, v, CTRL, RM, 0xF, BC);
-}
-template <int CTRL, int RM, bool BC>
-__device__ __forceinline__ float dppv(float v) {
-  return __builtin_bit_cast(float, dpp32<CTRL, RM, BC>(__builtin_bit_cast(int, v)));
-}
-template <int CTRL, int RM, bool BC>
-__device__ __forceinline__ double dppv(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = dpp32<CTRL, RM, BC>((int)(b & 0xFFFFFFFFLL));
-  const int hi = dpp32<CTRL, RM, BC>((int)(b >> 32));
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
-}
-__device__ __forceinline__ float lane63(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
-}
-__device__ __forceinline__ double lane63(double v) {
-  const long long b = __builtin_bit_cast(long long, v);
-  const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFLL), 63);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
-  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
 // Segmented scan over the 64 lanes of (f, v), where a set flag starts a new
@@ -110,21 +80,6 @@ __device__ __forceinline__ void lds_add(double* p, double v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void lds_add(float* p, float v) { *p += v; }
-
-// Streaming load through a global-address-space pointer: the store's arrays
-// are reached through the descriptor, so the compiler would otherwise emit
-// flat loads, which also count against the LDS wait counter and make every
-// LDS wait drain the prefetched entries.
-template <class T>
-__device__ __forceinline__ T gload_nt(const T* p) {
-  using GP = const __attribute__((address_space(1))) T*;
-  return __builtin_nontemporal_load((GP)p);
-}
-template <class T>
-__device__ __forceinline__ T gload(const T* p) {
-  using GP = const __attribute__((address_space(1))) T*;
-  return *(GP)p;
-}
 
 // Entries per lane in a window of c entries: Qw = ceil(c / 64) for lanes
 // below r = c - 64 (Qw - 1), Qw - 1 for the others.

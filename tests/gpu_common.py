@@ -50,7 +50,7 @@ def order_spread(A, b, k, wi=None, x0=None):
     return ref, spread
 
 
-def fp64_parity(h, sysm, tol=1e-8, maxit=5000, wi=None, storage="f64", layout=None):
+def fp64_parity(h, sysm, tol=1e-8, maxit=5000, wi=None, storage="f64", layout=None, **kw):
     """Check a float64 solve against Algorithm 1 (oracle):
 
     * the GPU meets the stop test and its iteration count is within one of
@@ -68,7 +68,7 @@ def fp64_parity(h, sysm, tol=1e-8, maxit=5000, wi=None, storage="f64", layout=No
     M = matrix(h, sysm.A, storage)
     if layout is not None:
         M.layout(**layout)
-    x, info, hist = plss.solve(h, M, sysm.b, tol=tol, maxit=maxit, wi=wi)
+    x, info, hist = plss.solve(h, M, sysm.b, tol=tol, maxit=maxit, wi=wi, **kw)
     assert info["status"] == 0, info
     k = info["iters"]
     ref, floor = order_spread(sysm.A, sysm.b, k, wi=wi)
@@ -78,7 +78,7 @@ def fp64_parity(h, sysm, tol=1e-8, maxit=5000, wi=None, storage="f64", layout=No
     full = O.plss_residual(sysm.A, sysm.b, tol=tol, maxit=maxit, wi=wi)
     assert abs(full.iters - k) <= 1
     k15 = min(15, k)
-    x15, i15, _ = plss.solve(h, M, sysm.b, tol=1e-300, maxit=k15, wi=wi)
+    x15, i15, _ = plss.solve(h, M, sysm.b, tol=1e-300, maxit=k15, wi=wi, **kw)
     r15 = O.plss_residual(sysm.A, sysm.b, tol=1e-300, maxit=k15, wi=wi)
     assert rel(x15, r15.x) <= 1e-12
     return x, info, M
