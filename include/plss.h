@@ -209,12 +209,15 @@ plss_status plss_solve_multi(plss_handle* h, const plss_matrix* A, int32_t nrhs,
 plss_status plss_kernel_times(plss_handle* h, double* ms4, int64_t* launches4);
 
 /* ---- request loop (continuous batching) ----
- * A server owns a host thread and its own stream on the handle's device.
+ * A server owns a host thread and its own streams on the handle's device.
  * Submitted systems wait until their device footprint fits under
  * hbm_budget_bytes and a slot is free, are uploaded and transposed on a side
  * stream, then join the running batch at the next launch boundary; all
- * admitted systems advance together.  Finished solutions are copied back and
- * their memory freed. */
+ * admitted systems advance together on the per-phase engine (opts.engine 0
+ * and 1 alike).  A request with opts.engine = 2 runs whole in one workgroup
+ * on a stream of its own beside the batch.  Finished solutions are copied
+ * back and their memory freed.  A served result equals the solve of the same
+ * system alone on the same engine, bit for bit. */
 plss_status plss_server_create(plss_handle* h, size_t hbm_budget_bytes, int32_t max_slots,
                                plss_server** out);
 /* Queue a system (A is copied; the caller's arrays are free after return).

@@ -1,15 +1,19 @@
 // Request loop with continuous batching.
 //
-// A server thread owns two streams of the handle's device.  Each pass of
+// A server thread owns three streams of the handle's device.  Each pass of
 // its loop enqueues one chunk of iterations for every admitted system on the
 // main stream, then - while that chunk runs - admits queued requests: their
 // device footprint must fit under the budget next to the admitted systems
 // and a slot must be free; admission uploads the matrix and builds its CSC
 // copy on the side stream.  After the chunk, finished systems are copied back
 // to host memory, their device memory is freed and their slot released, and
-// the systems admitted meanwhile join the next chunk.  A system's arithmetic
-// depends only on its own tiles, so its result does not depend on which
-// other systems share the launches.
+// the systems admitted meanwhile join the next chunk (the per-phase engine:
+// all in-flight systems share every launch, which keeps the whole GPU busy).
+// A request that asks for the single-workgroup engine (opts.engine = 2)
+// instead runs whole, one launch, on the third stream beside the chunks, and
+// retires when its event completes.  A system's arithmetic depends only on
+// its own data, so its result does not depend on which other systems share
+// the GPU.
 #include "serve.hpp"
 
 #include <chrono>
@@ -54,6 +58,7 @@ struct Req {
   plss_info info{};
   plss_status fail = PLSS_OK;
   double t_submit = 0, t_done = 0;
+  hipEvent_t done_ev = nullptr;  // single-workgroup solve finished (small systems)
 };
 
 }  // namespace
@@ -80,8 +85,8 @@ struct plss_server {
   std::vector<plss::Desc> h_desc;
   std::vector<int> free_slots;
   plss::ListSet lists;
-  int* d_small_ids = nullptr;  // slots of the small systems launched this pass
-  int* h_small_ids = nullptr;  // pinned staging of the same
+  hipStream_t small = nullptr;  // single-workgroup solves, beside the chunks on `main`
+  int* d_slot_ids = nullptr;     // slot i holds i: the system list of a one-system launch
 };
 
 namespace plss {
@@ -120,19 +125,27 @@ void rebuild_lists(plss_server* S) {
   S->lists.build(items, S->main);
 }
 
-// One persistent launch (per storage type) for the small systems that joined:
-// each workgroup runs its system to the end, ahead of this pass's chunk.
+// Small systems that joined run whole, one workgroup each, on the stream of
+// their own beside the chunks on `main`; an event marks each one's end.
 void launch_joined_small(plss_server* S, const std::vector<Req*>& joined) {
-  std::vector<int> s64, s32;
-  for (Req* r : joined)
-    if (r->run->small) (r->run->f32 ? s32 : s64).push_back(r->slot);
-  if (s64.empty() && s32.empty()) return;
-  int k = 0;
-  for (int v : s64) S->h_small_ids[k++] = v;
-  for (int v : s32) S->h_small_ids[k++] = v;
-  PLSS_HIP(hipMemcpyAsync(S->d_small_ids, S->h_small_ids, sizeof(int) * k, hipMemcpyHostToDevice, S->main));
-  launch_small(false, S->d_desc, S->d_small_ids, (int)s64.size(), S->main);
-  launch_small(true, S->d_desc, S->d_small_ids + s64.size(), (int)s32.size(), S->main);
+  for (Req* r : joined) {
+    if (!r->run->small) continue;
+    launch_small(r->run->f32, S->d_desc, S->d_slot_ids + r->slot, 1, S->small);
+    if (!r->done_ev) PLSS_HIP(hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming));
+    PLSS_HIP(hipEventRecord(r->done_ev, S->small));
+  }
+}
+
+// A single-workgroup solve has ended (its memory may then be released).
+bool small_finished(Req* r) {
+  const hipError_t e = hipEventQuery(r->done_ev);
+  if (e == hipSuccess) return true;
+  if (e != hipErrorNotReady) {
+    set_error(std::string("hipEventQuery: ") + hipGetErrorString(e));
+    throw DeviceError();
+  }
+  (void)hipGetLastError();
+  return false;
 }
 
 // Upload and prepare one request on the side stream (server thread).
@@ -147,6 +160,9 @@ void prepare(plss_server* S, Req* r) {
   r->M = matrix_create(S->h, &c, r->storage, S->side);  // holds a handle reference
   r->run.reset(new SysRun());
   r->run->setup(r->M, r->b.data(), &r->o, 1, S->d_slots + r->slot, nullptr);
+  // throughput: served systems are stepped together on the per-phase engine
+  // unless the request asks for the single-workgroup engine (engine 2)
+  if (r->o.engine != 2) r->run->small = false;
   r->run->upload(r->b.data(), r->o.x0, r->o.wi_diag, S->side);
   PLSS_HIP(hipMemcpyAsync(S->d_slots + r->slot, &r->run->st0, sizeof(State), hipMemcpyHostToDevice, S->side));
   PLSS_HIP(hipMemcpyAsync(S->d_desc + r->slot, &r->run->desc, sizeof(Desc), hipMemcpyHostToDevice, S->side));
@@ -158,6 +174,11 @@ void prepare(plss_server* S, Req* r) {
 }
 
 void release(plss_server* S, Req* r) {
+  if (r->done_ev) {
+    (void)hipEventSynchronize(r->done_ev);  // a single-workgroup solve may still run on this memory
+    (void)hipEventDestroy(r->done_ev);
+    r->done_ev = nullptr;
+  }
   r->run.reset();
   if (r->M) {
     matrix_destroy(r->M);
@@ -282,7 +303,18 @@ void loop(plss_server* S) {
       keep.clear();
       bool retired = false;
       for (Req* r : S->active) {
-        const State& st = S->h_slots[r->slot];
+        State small_st;
+        const State* stp = &S->h_slots[r->slot];
+        if (r->run->small) {
+          // the chunk's state copy does not order after the other stream
+          if (!small_finished(r)) {
+            keep.push_back(r);
+            continue;
+          }
+          PLSS_HIP(hipMemcpy(&small_st, S->d_slots + r->slot, sizeof(State), hipMemcpyDeviceToHost));
+          stp = &small_st;
+        }
+        const State& st = *stp;
         if (!st.final_done) {
           keep.push_back(r);
           continue;
@@ -308,6 +340,9 @@ void loop(plss_server* S) {
       if (retired) {
         S->cv_done.notify_all();
         if (!S->active.empty()) rebuild_lists(S);
+      } else if (S->lists.nsys == 0 && joining.empty()) {
+        // only single-workgroup solves in flight: do not spin on their events
+        std::this_thread::sleep_for(std::chrono::microseconds(100));
       }
     } catch (...) {
       // device failure: fail everything still admitted or queued
@@ -348,18 +383,21 @@ plss_server* server_create(plss_handle* h, size_t budget, int max_slots) {
     PLSS_HIP(hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking));
     S->d_slots = static_cast<State*>(dmalloc(sizeof(State) * max_slots));
     S->d_desc = static_cast<Desc*>(dmalloc(sizeof(Desc) * max_slots));
-    S->d_small_ids = static_cast<int*>(dmalloc(sizeof(int) * max_slots));
-    PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&S->h_small_ids), sizeof(int) * max_slots, hipHostMallocDefault));
+    PLSS_HIP(hipStreamCreateWithFlags(&S->small, hipStreamNonBlocking));
+    S->d_slot_ids = static_cast<int*>(dmalloc(sizeof(int) * max_slots));
+    std::vector<int> ids(max_slots);
+    for (int i = 0; i < max_slots; ++i) ids[i] = i;
+    PLSS_HIP(hipMemcpy(S->d_slot_ids, ids.data(), sizeof(int) * max_slots, hipMemcpyHostToDevice));
     PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&S->h_slots), sizeof(State) * max_slots, hipHostMallocDefault));
     std::memset(S->h_slots, 0, sizeof(State) * max_slots);
   } catch (...) {
     dfree(S->d_slots);
     dfree(S->d_desc);
-    dfree(S->d_small_ids);
+    dfree(S->d_slot_ids);
     if (S->h_slots) (void)hipHostFree(S->h_slots);
-    if (S->h_small_ids) (void)hipHostFree(S->h_small_ids);
     if (S->main) (void)hipStreamDestroy(S->main);
     if (S->side) (void)hipStreamDestroy(S->side);
+    if (S->small) (void)hipStreamDestroy(S->small);
     delete S;
     (void)hipSetDevice(prev);
     throw;
@@ -471,17 +509,18 @@ void server_destroy(plss_server* S) {
   int prev = 0;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(S->h->device);
+  (void)hipStreamSynchronize(S->small);
   for (auto& kv : S->reqs) {
     release(S, kv.second);
     delete kv.second;
   }
   dfree(S->d_slots);
   dfree(S->d_desc);
-  dfree(S->d_small_ids);
+  dfree(S->d_slot_ids);
   if (S->h_slots) (void)hipHostFree(S->h_slots);
-  if (S->h_small_ids) (void)hipHostFree(S->h_small_ids);
   (void)hipStreamDestroy(S->main);
   (void)hipStreamDestroy(S->side);
+  (void)hipStreamDestroy(S->small);
   plss_handle* h = S->h;
   delete S;
   handle_release(h);

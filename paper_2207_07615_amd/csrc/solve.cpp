@@ -211,10 +211,14 @@ char* Workspace::pin_block(size_t bytes) {
 }
 
 Workspace::~Workspace() {
+  if (aux) (void)hipStreamSynchronize(aux);
   dfree(dev);
   if (pin) (void)hipHostFree(pin);
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);
+  if (ready) (void)hipEventDestroy(ready);
+  if (small_done) (void)hipEventDestroy(small_done);
+  if (aux) (void)hipStreamDestroy(aux);
   for (auto e : iter_events) (void)hipEventDestroy(e);
 }
 
@@ -223,6 +227,9 @@ Workspace& workspace(plss_handle* h) {
     std::unique_ptr<Workspace> w(new Workspace());
     PLSS_HIP(hipEventCreate(&w->t0));
     PLSS_HIP(hipEventCreate(&w->t1));
+    PLSS_HIP(hipEventCreateWithFlags(&w->ready, hipEventDisableTiming));
+    PLSS_HIP(hipEventCreateWithFlags(&w->small_done, hipEventDisableTiming));
+    PLSS_HIP(hipStreamCreateWithFlags(&w->aux, hipStreamNonBlocking));
     h->ws = w.release();
   }
   return *h->ws;
@@ -232,7 +239,10 @@ void workspace_free(Workspace* w) { delete w; }
 
 BatchRunner::BatchRunner(plss_handle* h) : h_(h), ws_(workspace(h)) {}
 
-BatchRunner::~BatchRunner() = default;
+BatchRunner::~BatchRunner() {
+  // after an error the second stream may still run on workspace memory
+  if (aux_used_) (void)hipStreamSynchronize(ws_.aux);
+}
 
 // ------------------------------------------------------------------ launch lists
 
@@ -418,19 +428,25 @@ void BatchRunner::run(hipStream_t s, bool timing, int chunk_req) {
     else (runs_[i]->f32 ? small32 : small64).push_back(i);
   }
   hipEvent_t t0 = ws_.t0, t1 = ws_.t1;
-  if (!small64.empty() || !small32.empty()) {
-    // one persistent launch per storage type; each workgroup solves its system
+  PLSS_HIP(hipEventRecord(t0, s));
+  const bool any_small = !small64.empty() || !small32.empty();
+  if (any_small) {
+    // one persistent launch per storage type on the second stream, after the
+    // uploads; each workgroup solves its system while the per-phase launches
+    // of the other systems run on `s`
     int k = 0;
     for (int i : small64) h_small_[k++] = i;
     for (int i : small32) h_small_[k++] = i;
     PLSS_HIP(hipMemcpyAsync(d_small_, h_small_, sizeof(int) * k, hipMemcpyHostToDevice, s));
-    PLSS_HIP(hipEventRecord(t0, s));
-    launch_small(false, d_desc_, d_small_, (int)small64.size(), s);
-    launch_small(true, d_desc_, d_small_ + small64.size(), (int)small32.size(), s);
-  } else {
-    PLSS_HIP(hipEventRecord(t0, s));
+    PLSS_HIP(hipEventRecord(ws_.ready, s));
+    PLSS_HIP(hipStreamWaitEvent(ws_.aux, ws_.ready, 0));
+    aux_used_ = true;
+    launch_small(false, d_desc_, d_small_, (int)small64.size(), ws_.aux);
+    launch_small(true, d_desc_, d_small_ + small64.size(), (int)small32.size(), ws_.aux);
+    PLSS_HIP(hipEventRecord(ws_.small_done, ws_.aux));
   }
   if (active.empty()) {
+    PLSS_HIP(hipStreamWaitEvent(s, ws_.small_done, 0));
     PLSS_HIP(hipMemcpyAsync(h_state_, d_state_, sizeof(State) * ns, hipMemcpyDeviceToHost, s));
     PLSS_HIP(hipEventRecord(t1, s));
     PLSS_HIP(hipEventSynchronize(t1));
@@ -487,6 +503,11 @@ void BatchRunner::run(hipStream_t s, bool timing, int chunk_req) {
       if (!active.empty()) build_lists(active, s);
     }
     if (chunk_req <= 0) chunk = std::min(cmax, chunk * 2);
+  }
+  if (any_small) {
+    // the single-workgroup systems' final states
+    PLSS_HIP(hipStreamWaitEvent(s, ws_.small_done, 0));
+    PLSS_HIP(hipMemcpyAsync(h_state_, d_state_, sizeof(State) * ns, hipMemcpyDeviceToHost, s));
   }
   PLSS_HIP(hipEventRecord(t1, s));
   PLSS_HIP(hipEventSynchronize(t1));

@@ -67,6 +67,8 @@ struct Workspace {
   size_t pin_cap = 0;
   ListSet lists;
   hipEvent_t t0 = nullptr, t1 = nullptr;
+  hipEvent_t ready = nullptr, small_done = nullptr;
+  hipStream_t aux = nullptr;             // second stream: single-workgroup solves beside the phases
   std::vector<hipEvent_t> iter_events;  // 5 per timed iteration
   char* dev_block(size_t bytes);
   char* pin_block(size_t bytes);
@@ -103,6 +105,7 @@ class BatchRunner {
   int* d_small_ = nullptr;  // systems of the single-workgroup engine (float64 first, then float32)
   State* h_state_ = nullptr;
   int* h_small_ = nullptr;
+  bool aux_used_ = false;  // work was enqueued on the workspace's second stream
   float elapsed_ms_ = 0;
 };
 

@@ -35,17 +35,28 @@ def wait(srv, req, timeout=120.0):
         time.sleep(0.002)
 
 
+def single_fits(A, kind):
+    """The single-workgroup engine holds x, r, p, y and the row pointers in LDS."""
+    vb = 4 if kind == "f32" else 8
+    return 8 * A.n + vb * (A.m + 2 * A.n) + 4 * (A.m + A.n + 40) <= 156 * 1024 - 1024
+
+
 def test_served_results_equal_alone(h):
     """Requests arriving while others run join the running batch; each
-    result is bit-identical to the same system solved alone."""
+    result is bit-identical to the same system solved alone on the same
+    engine (the per-phase engine, or the single-workgroup engine for the
+    requests that ask for it)."""
     import paper_2207_07615_amd as plss
     say("serve mix")
     systems = gen.stream_systems(10, m_lo=1e3, m_hi=3e4)
     kinds = ["f64" if i % 2 == 0 else "f32" for i in range(len(systems))]
     srv = plss.Server(h, hbm_budget_bytes=8 << 30, max_slots=16)
     reqs = []
+    n_single = 0
     for i, (s, kind) in enumerate(zip(systems, kinds)):
-        kw = dict(tol=s.tol, maxit=s.A.n + 1000)
+        engine = "single" if i % 4 != 2 and single_fits(s.A, kind) else "multi"
+        n_single += engine == "single"
+        kw = dict(tol=s.tol, maxit=s.A.n + 1000, engine=engine)
         if kind == "f32":
             A32 = s.A.astype(np.float32)
             b = gen.rhs(A32, s.xstar)
@@ -61,10 +72,12 @@ def test_served_results_equal_alone(h):
         M = matrix(h, A, kind)
         extra = dict(refine=True, inner_tol=1e-4) if kind == "f32" else {}
         xa, ia, _ = plss.solve(h, M, b, **kw, **extra)
-        say(f"  {kind} m={A.m} iters={info['iters']} status={info['status_name']} latency_ms={info['ms']:.1f}")
+        say(f"  {kind} {kw['engine']} m={A.m} iters={info['iters']} status={info['status_name']} "
+            f"latency_ms={info['ms']:.1f}")
         assert info["status"] == ia["status"]
         assert info["iters"] == ia["iters"]
         np.testing.assert_array_equal(x, xa)
+    assert n_single >= 1
 
 
 def test_small_budget_queues_requests(h):
