@@ -58,9 +58,10 @@ def recorded_traffic(kernel_index, layout):
     path = os.path.join(ROOT, "profiles", "large_fp64_traffic.txt")
     try:
         kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith("#"))
-        src = os.path.join(ROOT, "paper_2207_07615_amd", "csrc", kv["source"])
-        sha = hashlib.sha1(open(src, "rb").read()).hexdigest()[:12]
-        if kv.get("source_sha1_12") != sha or kv.get("layout") != layout:
+        h = hashlib.sha1()
+        for name in kv["sources"].split(","):
+            h.update(open(os.path.join(ROOT, "paper_2207_07615_amd", "csrc", name), "rb").read())
+        if kv.get("sources_sha1_12") != h.hexdigest()[:12] or kv.get("layout") != layout:
             return None
         sfx = "" if kernel_index == 0 else "_t"
         return (float(kv["fetch_kib" + sfx]) * float(kv["fetch_scale"]) +
