@@ -238,7 +238,9 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
     x = static_cast<const Vin*>(d->p) + sv.colbase;
     xlen = sv.ncols;
   }
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  // the wave index is uniform: wave bounds come through scalar loads and the
+  // window loop runs on scalar control flow
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 
   const int* __restrict__ seg = sv.seg + (size_t)u * S;
   const int* __restrict__ wsp = sv.wsp + (size_t)u * S * kSWaves;

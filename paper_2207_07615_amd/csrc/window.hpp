@@ -135,20 +135,22 @@ __device__ __forceinline__ void sum_window(const unsigned* __restrict__ pk, int 
   Acc prods[kQmax];
 #pragma unroll
   for (int q = 0; q < kQmax; ++q) prods[q] = Acc(vv[q]) * xs[pv[q] & (SW - 1)];
+  // slots past the lane's entries leave the state unchanged (selects, so the
+  // wave runs the slots without branching)
 #pragma unroll
   for (int q = 0; q < kQmax; ++q) {
-    if (q < mine) {
-      const int rr = (int)(pv[q] >> 16);
-      const bool brk = rr != cur;
-      const bool ended = brk && cur >= 0;  // the run of `cur` ends before this entry
-      if (ended && hend) lds_add(&s_acc[cur], acc);
-      const bool first = ended && !hend;   // the lane's first run end waits for the carry
-      fv = first ? acc : fv;
-      fr = first ? cur : fr;
-      hend = hend || ended;
-      acc = brk ? prods[q] : acc + prods[q];
-      cur = rr;
-    }
+    const bool act = q < mine;
+    const int rr = (int)(pv[q] >> 16);
+    const bool brk = act && rr != cur;
+    const bool ended = brk && cur >= 0;  // the run of `cur` ends before this entry
+    if (ended && hend) lds_add(&s_acc[cur], acc);
+    const bool first = ended && !hend;   // the lane's first run end waits for the carry
+    fv = first ? acc : fv;
+    fr = first ? cur : fr;
+    hend = hend || ended;
+    const Acc sum = acc + prods[q];
+    acc = brk ? prods[q] : (act ? sum : acc);
+    cur = act ? rr : cur;
   }
   if (cur >= 0 && nrow != cur) {
     if (!hend) {
