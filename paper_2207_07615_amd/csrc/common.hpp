@@ -50,12 +50,17 @@ constexpr int kSThreads = 1024;
 constexpr int kMaxStripes = 8192;  // stripes per store (cursor table of the builder in LDS)
 constexpr size_t kSmallLds = 156 * 1024;  // LDS for r, p, y of a single-workgroup solve
 constexpr long long kSmallNnz = 1 << 18;  // automatic single-workgroup solves up to this many entries
-constexpr int kStorePad = 64;      // entries allocated past the end of a striped store: a
-                                   // window's last slot is loaded by every lane of the wave
+constexpr int kStorePad = 64;      // records allocated past the end of a striped store: a
+                                   // float32 window's last slot is loaded by every lane
+
+// Entry records of a striped store, in 32-bit words: a float64 value in
+// words 0-1 and the packed (row in unit) << 16 | (column in stripe) in word
+// 2; a float32 value in word 0 and the packed word in word 1.  One load
+// instruction per lane brings a whole entry.
+constexpr int rec_words(bool f32) { return f32 ? 2 : 3; }
 
 struct StripeView {
-  const unsigned* pk;          // entries: (row in unit) << 16 | (column in stripe)
-  const void* val;             // values (storage precision)
+  const unsigned* rec;         // entry records (rec_words per entry)
   const int* urow;             // nunits + 1 row starts of the units
   const int* seg;              // nunits * S + 1 entry starts of the (unit, stripe) segments
   const int* wsp;              // 16 row-aligned wave starts per segment

@@ -146,8 +146,7 @@ void auto_layout(long long m, long long n, long long nnz, bool f32, bool* a_stri
 }
 
 static void free_stripes(PlssStripes& st) {
-  dfree(st.pk);
-  dfree(st.val);
+  dfree(st.rec);
   dfree(st.urow);
   dfree(st.seg);
   dfree(st.wsp);
@@ -155,8 +154,7 @@ static void free_stripes(PlssStripes& st) {
 }
 
 void fill_stripe_view(const PlssStripes& st, StripeView* v) {
-  v->pk = st.pk;
-  v->val = st.val;
+  v->rec = st.rec;
   v->urow = st.urow;
   v->seg = st.seg;
   v->wsp = st.wsp;
@@ -182,14 +180,16 @@ static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, int
   PlssStripes st;
   int* cnt = nullptr;
   void* work = nullptr;
+  unsigned* pk = nullptr;  // CSR-ordered entries of the segments, before the records
+  void* val = nullptr;
   try {
     std::vector<int> urow(nunits + 1);
     for (int u = 0; u <= nunits; ++u) urow[u] = (int)std::min<long long>(rows, (long long)u * R);
     st.urow = static_cast<int*>(dmalloc(sizeof(int) * urow.size()));
     st.seg = static_cast<int*>(dmalloc(sizeof(int) * (size_t)(nseg + 1)));
     st.wsp = static_cast<int*>(dmalloc(sizeof(int) * (size_t)std::max<long long>(nseg * 16, 1)));
-    st.pk = static_cast<unsigned*>(dmalloc(sizeof(unsigned) * (size_t)std::max<long long>(nnz, 1)));
-    st.val = dmalloc(vb * (size_t)std::max<long long>(nnz, 1));
+    pk = static_cast<unsigned*>(dmalloc(sizeof(unsigned) * (size_t)std::max<long long>(nnz, 1)));
+    val = dmalloc(vb * (size_t)std::max<long long>(nnz, 1));
     cnt = static_cast<int*>(dmalloc(sizeof(int) * (size_t)std::max<long long>(nseg, 1)));
     work = dmalloc(sizeof(long long) * (size_t)((nseg + 1023) / 1024 + 2));
     PLSS_HIP(hipMemcpyAsync(st.urow, urow.data(), sizeof(int) * urow.size(), hipMemcpyHostToDevice, s));
@@ -202,34 +202,27 @@ static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, int
       set_error("striped store: entry count mismatch");
       throw DeviceError();
     }
-    st_scatter(src.ptr, src.idx, src.val, f32, nunits, st.urow, st.seg, S, colbase, sw, st.pk, st.val, s);
-    st_split(st.pk, st.seg, nseg, st.wsp, s);
-    // lane-interleaved windows (out of place, then the CSR-ordered copy goes)
-    unsigned* ipk = static_cast<unsigned*>(dmalloc(sizeof(unsigned) * (size_t)(nnz + kStorePad)));
-    void* ival = nullptr;
-    try {
-      ival = dmalloc(vb * (size_t)(nnz + kStorePad));
-      PLSS_HIP(hipMemsetAsync(ipk + nnz, 0, sizeof(unsigned) * kStorePad, s));
-      PLSS_HIP(hipMemsetAsync(static_cast<char*>(ival) + vb * nnz, 0, vb * kStorePad, s));
-      st_interleave(st.pk, st.val, f32, st.seg, st.wsp, nseg, ipk, ival, s);
-      PLSS_HIP(hipStreamSynchronize(s));
-    } catch (...) {
-      dfree(ipk);
-      dfree(ival);
-      throw;
-    }
-    dfree(st.pk);
-    dfree(st.val);
-    st.pk = ipk;
-    st.val = ival;
+    st_scatter(src.ptr, src.idx, src.val, f32, nunits, st.urow, st.seg, S, colbase, sw, pk, val, s);
+    st_split(pk, st.seg, nseg, st.wsp, s);
+    // lane-interleaved windows of entry records (the padding past the end
+    // is zero: row 0, column 0, value 0)
+    const size_t words = (size_t)rec_words(f32);
+    st.rec = static_cast<unsigned*>(dmalloc(sizeof(unsigned) * words * (size_t)(nnz + kStorePad)));
+    PLSS_HIP(hipMemsetAsync(st.rec + words * (size_t)nnz, 0, sizeof(unsigned) * words * kStorePad, s));
+    st_interleave(pk, val, f32, st.seg, st.wsp, nseg, st.rec, s);
+    PLSS_HIP(hipStreamSynchronize(s));
   } catch (...) {
     dfree(cnt);
     dfree(work);
+    dfree(pk);
+    dfree(val);
     free_stripes(st);
     throw;
   }
   dfree(cnt);
   dfree(work);
+  dfree(pk);
+  dfree(val);
   st.nunits = nunits;
   st.S = S;
   st.colbase = colbase;

@@ -28,8 +28,7 @@ struct PlssDir {
 // A striped store of one direction (stripe.hip): units of unit_rows rows,
 // stripes of sw columns of the gathered vector.
 struct PlssStripes {
-  unsigned* pk = nullptr;  // nnz packed (row in unit, column in stripe)
-  void* val = nullptr;     // nnz values (storage precision)
+  unsigned* rec = nullptr; // nnz + kStorePad entry records (rec_words each)
   int* urow = nullptr;     // nunits + 1
   int* seg = nullptr;      // nunits * S + 1
   int* wsp = nullptr;      // nunits * S * 16

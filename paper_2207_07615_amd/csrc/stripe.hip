@@ -161,13 +161,24 @@ __global__ void k_st_split(const unsigned* __restrict__ pk, const int* __restric
   }
 }
 
-// Reorder every window of every wave range lane-interleaved: the lane's
-// k-th entry (its entries are consecutive in CSR order) moves to window
-// start + 64 k + lane.  One wave per (segment, wave) range.
+// Reorder every window of every wave range lane-interleaved into entry
+// records: the lane's k-th entry (its entries are consecutive in CSR order)
+// goes to record window start + 64 k + lane.  One wave per (segment, wave)
+// range.
+__device__ __forceinline__ void put_rec(unsigned* rec, long long i, unsigned pk, double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  rec[3 * i] = (unsigned)b;
+  rec[3 * i + 1] = (unsigned)(b >> 32);
+  rec[3 * i + 2] = pk;
+}
+__device__ __forceinline__ void put_rec(unsigned* rec, long long i, unsigned pk, float v) {
+  rec[2 * i] = __builtin_bit_cast(unsigned, v);
+  rec[2 * i + 1] = pk;
+}
 template <class Val>
 __global__ void k_st_interleave(const unsigned* __restrict__ pk, const Val* __restrict__ val,
                                 const int* __restrict__ seg, const int* __restrict__ wsp, long long nseg,
-                                unsigned* __restrict__ opk, Val* __restrict__ oval) {
+                                unsigned* __restrict__ rec) {
   const int lane = threadIdx.x & 63;
   const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
   for (long long q = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < nseg * kSWaves; q += nw) {
@@ -181,10 +192,7 @@ __global__ void k_st_interleave(const unsigned* __restrict__ pk, const Val* __re
       const int Qw = (c + 63) >> 6, r = c - 64 * (Qw - 1);
       const int mine = lane < r ? Qw : Qw - 1;
       const int start = lane < r ? lane * Qw : r * Qw + (lane - r) * (Qw - 1);
-      for (int k = 0; k < mine; ++k) {
-        opk[base + 64 * k + lane] = pk[base + start + k];
-        oval[base + 64 * k + lane] = val[base + start + k];
-      }
+      for (int k = 0; k < mine; ++k) put_rec(rec, base + 64 * k + lane, pk[base + start + k], val[base + start + k]);
     }
   }
 }
@@ -219,8 +227,7 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
   const int blk = tb ? (ent.y >> 24) : 0;
   const int u = tb ? (ent.y & 0xFFFFFF) : ent.y;
   const StripeView& sv = tb ? d->sb[blk] : d->sa;
-  const unsigned* __restrict__ pk = sv.pk;
-  const Val* __restrict__ val = static_cast<const Val*>(sv.val);
+  const unsigned* __restrict__ rec = sv.rec;
   const int S = sv.S;
   const int r0 = sv.urow[u], nr = sv.urow[u + 1] - r0;
   const Vin* __restrict__ x;
@@ -258,20 +265,18 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
   // cur's bounds then take stripe s + 3.  The loop is unrolled by three so
   // the sets keep fixed registers instead of being copied every stripe.
   int wsA, weA, wsB, weB, wsC, weC;
-  unsigned pA[kQmax], pB[kQmax], pC[kQmax];
-  Val vA[kQmax], vB[kQmax], vC[kQmax];
+  Ent<Val> eA[kQmax], eB[kQmax], eC[kQmax];
   bounds(0, wsA, weA);
   bounds(1, wsB, weB);
   bounds(2, wsC, weC);
-  load_window(pk, val, wsA, min(64 * range_q(weA - wsA), weA - wsA), pA, vA);
-  load_window(pk, val, wsB, min(64 * range_q(weB - wsB), weB - wsB), pB, vB);
+  load_window<Val>(rec, wsA, min(64 * range_q(weA - wsA), weA - wsA), eA);
+  load_window<Val>(rec, wsB, min(64 * range_q(weB - wsB), weB - wsB), eB);
 
   for (int i = threadIdx.x; i < nr; i += kST) s_acc[i] = Acc(0);
   for (int j = threadIdx.x; j < SW; j += kST) s_x[0][j] = j < xlen ? Acc(gload(&x[j])) : Acc(0);
   __syncthreads();
 
-  auto stripe = [&](int s, int& ws0, int& we0, const unsigned* cpv, const Val* cvv, int ws2, int we2,
-                    unsigned* mpv, Val* mvv) {
+  auto stripe = [&](int s, int& ws0, int& we0, const Ent<Val>* ce, int ws2, int we2, Ent<Val>* me) {
     // the next stripe's slice of x travels in registers during this stripe
     Acc nx[SW / kST];
 #pragma unroll
@@ -281,20 +286,21 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
     }
     int ws3, we3;
     bounds(s + 3, ws3, we3);
-    load_window(pk, val, ws2, min(64 * range_q(we2 - ws2), we2 - ws2), mpv, mvv);
+    load_window<Val>(rec, ws2, min(64 * range_q(we2 - ws2), we2 - ws2), me);
 
     const Acc* __restrict__ xs = s_x[s & 1];
     if (we0 > ws0) {
       const int Q = range_q(we0 - ws0);
-      Acc wc = Acc(0);  // open row sum carried from the previous window
-      sum_window<SW, Val, Acc>(pk, ws0, min(ws0 + 64 * Q, we0), we0, cpv, cvv, xs, s_acc, wc);
+      Acc wc = Acc(0);  // run open at the end of the previous window
+      int wr = -1;
+      sum_window<SW, Val, Acc>(min(64 * Q, we0 - ws0), ce, xs, s_acc, wc, wr);
       for (int base = ws0 + 64 * Q; base < we0; base += 64 * Q) {
-        const int wend = min(base + 64 * Q, we0);
-        unsigned pv[kQmax];
-        Val vv[kQmax];
-        load_window(pk, val, base, wend - base, pv, vv);
-        sum_window<SW, Val, Acc>(pk, base, wend, we0, pv, vv, xs, s_acc, wc);
+        const int c = min(64 * Q, we0 - base);
+        Ent<Val> ev[kQmax];
+        load_window<Val>(rec, base, c, ev);
+        sum_window<SW, Val, Acc>(c, ev, xs, s_acc, wc, wr);
       }
+      flush_open(s_acc, wc, wr);
     }
 #pragma unroll
     for (int q = 0; q < SW / kST; ++q) s_x[(s + 1) & 1][q * kST + threadIdx.x] = nx[q];
@@ -303,11 +309,11 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
     __syncthreads();
   };
   for (int s = 0; s < S; s += 3) {
-    stripe(s, wsA, weA, pA, vA, wsC, weC, pC, vC);
+    stripe(s, wsA, weA, eA, wsC, weC, eC);
     if (s + 1 >= S) break;
-    stripe(s + 1, wsB, weB, pB, vB, wsA, weA, pA, vA);
+    stripe(s + 1, wsB, weB, eB, wsA, weA, eA);
     if (s + 2 >= S) break;
-    stripe(s + 2, wsC, weC, pC, vC, wsB, weB, pB, vB);
+    stripe(s + 2, wsC, weC, eC, wsB, weB, eB);
   }
 
   // epilogue over the unit's rows
@@ -398,15 +404,13 @@ void st_split(const unsigned* pk, const int* d_seg, long long nseg, int* d_wsp, 
 }
 
 void st_interleave(const unsigned* pk, const void* val, bool f32, const int* d_seg, const int* d_wsp, long long nseg,
-                   unsigned* opk, void* oval, hipStream_t s) {
+                   unsigned* rec, hipStream_t s) {
   if (nseg <= 0) return;
   const int grid = st_grid(nseg * kSWaves * 64, 256);
   if (f32)
-    k_st_interleave<float><<<grid, 256, 0, s>>>(pk, static_cast<const float*>(val), d_seg, d_wsp, nseg, opk,
-                                               static_cast<float*>(oval));
+    k_st_interleave<float><<<grid, 256, 0, s>>>(pk, static_cast<const float*>(val), d_seg, d_wsp, nseg, rec);
   else
-    k_st_interleave<double><<<grid, 256, 0, s>>>(pk, static_cast<const double*>(val), d_seg, d_wsp, nseg, opk,
-                                                static_cast<double*>(oval));
+    k_st_interleave<double><<<grid, 256, 0, s>>>(pk, static_cast<const double*>(val), d_seg, d_wsp, nseg, rec);
   PLSS_HIP(hipGetLastError());
 }
 

@@ -5,6 +5,11 @@
 
 namespace plss {
 
+// 2- and 3-word vectors at 4-byte alignment (entry records of the striped
+// stores)
+typedef unsigned u32x2 __attribute__((ext_vector_type(2), aligned(4)));
+typedef unsigned u32x3 __attribute__((ext_vector_type(3), aligned(4)));
+
 // DPP controls of GFX9-family wave64 cross-lane moves
 constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
 constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143, kWaveShl1 = 0x130, kWaveShr1 = 0x138;
@@ -60,6 +65,14 @@ __device__ __forceinline__ T gload(const T* p) {
 template <class T>
 __device__ __forceinline__ T gload_nt(const T* p) {
   using GP = const __attribute__((address_space(1))) T*;
+  return __builtin_nontemporal_load((GP)p);
+}
+__device__ __forceinline__ u32x2 gload_nt2(const unsigned* p) {
+  using GP = const __attribute__((address_space(1))) u32x2*;
+  return __builtin_nontemporal_load((GP)p);
+}
+__device__ __forceinline__ u32x3 gload_nt3(const unsigned* p) {
+  using GP = const __attribute__((address_space(1))) u32x3*;
   return __builtin_nontemporal_load((GP)p);
 }
 template <class T>

@@ -67,66 +67,74 @@ __device__ __forceinline__ int range_q(int len) {
   return Q > kQmax ? kQmax : (Q < 1 ? 1 : Q);
 }
 
+// One entry record in registers: (value, packed word) loaded by one
+// instruction and taken apart where it is used.
+template <class Val> struct EntOf;
+template <> struct EntOf<double> { using type = u32x3; };
+template <> struct EntOf<float> { using type = u32x2; };
+template <class Val> using Ent = typename EntOf<Val>::type;
+__device__ __forceinline__ unsigned ent_pk(u32x3 e) { return e.z; }
+__device__ __forceinline__ unsigned ent_pk(u32x2 e) { return e.y; }
+__device__ __forceinline__ double ent_val(u32x3 e) {
+  return __builtin_bit_cast(double, ((unsigned long long)e.y << 32) | e.x);
+}
+__device__ __forceinline__ float ent_val(u32x2 e) { return __builtin_bit_cast(float, e.x); }
+
 // One lane-interleaved window of c entries into registers (the lane's
-// entries in CSR order).  Float values: every lane loads all Qw =
-// ceil(c / 64) slots, so the loads depend on wave-uniform values only and
-// share one address; a lane without an entry in the last slot reads one of
-// the 63 entries past the window (the store has kStorePad entries of padding
-// past its end) and never uses it.  Double values: only the lane's own
-// slots are loaded (the uniform form needs more registers than the double
-// kernel has to spare, and measured 1-2 % slower there).
+// entries in CSR order), one record load per entry; a slot without an entry
+// holds row 0xFFFF, column 0xFFFF and value 0.  Float values: every lane
+// loads all Qw = ceil(c / 64) slots, so the loads depend on wave-uniform
+// values only; a lane without an entry in the last slot reads one of the 63
+// records past the window (the store has kStorePad records of padding past
+// its end) and never uses it.  Double values: only the lane's own slots are
+// loaded (the uniform form needs more registers than the double kernel has
+// to spare).
 template <class Val>
-__device__ __forceinline__ void load_window(const unsigned* __restrict__ pk, const Val* __restrict__ val, int base,
-                                            int c, unsigned* pv, Val* vv) {
+__device__ __forceinline__ void load_window(const unsigned* __restrict__ rec, int base, int c, Ent<Val>* e) {
   const int lane = threadIdx.x & 63;
   if constexpr (sizeof(Val) == 4) {
     const int Qw = (c + 63) >> 6;
-    const unsigned* pp = pk + base + lane;
-    const Val* vp = val + base + lane;
+    const unsigned* wp = rec + 2 * (size_t)(base + lane);
 #pragma unroll
-    for (int q = 0; q < kQmax; ++q) {
-      if (q < Qw) {
-        pv[q] = gload_nt(pp + 64 * q);
-        vv[q] = gload_nt(vp + 64 * q);
-      } else {
-        pv[q] = 0xFFFFFFFFu;
-        vv[q] = Val(0);
-      }
-    }
+    for (int q = 0; q < kQmax; ++q) e[q] = q < Qw ? gload_nt2(wp + 128 * q) : u32x2{0u, 0xFFFFFFFFu};
   } else {
     const int mine = c > 0 ? win_count(c, lane) : 0;
+    const unsigned* wp = rec + 3 * (size_t)(base + lane);
 #pragma unroll
-    for (int q = 0; q < kQmax; ++q) {
-      if (q < mine) {
-        pv[q] = gload_nt(&pk[base + 64 * q + lane]);
-        vv[q] = gload_nt(&val[base + 64 * q + lane]);
-      } else {
-        pv[q] = 0xFFFFFFFFu;
-        vv[q] = Val(0);
-      }
-    }
+    for (int q = 0; q < kQmax; ++q) e[q] = q < mine ? gload_nt3(wp + 192 * q) : u32x3{0u, 0u, 0xFFFFFFFFu};
   }
 }
 
-// Row sums of one window [base, wend) of a wave range ending at we, added
-// to s_acc.  wc: open row sum carried in from the previous window, and out
-// to the next one.
+// Row sums of one window of c > 0 entries of a wave range, added to s_acc.
+// The run that is open at the window's end (the last lane's final run,
+// with the carries of the lanes before it) is not written here: it goes out
+// in (wc, wr) = (partial sum, row), and the next window of the range adds it
+// to its first run if that run continues the row, or writes it first if
+// not; after the range's last window the caller writes it (flush_open).
+// No global load is needed to find where that run ends.  On entry wr = -1
+// if nothing is carried.
 template <int SW, class Val, class Acc>
-__device__ __forceinline__ void sum_window(const unsigned* __restrict__ pk, int base, int wend, int we,
-                                           const unsigned* pv, const Val* vv, const Acc* __restrict__ xs,
-                                           Acc* s_acc, Acc& wc) {
+__device__ __forceinline__ void sum_window(int c, const Ent<Val>* e, const Acc* __restrict__ xs, Acc* s_acc,
+                                           Acc& wc, int& wr) {
   const int lane = threadIdx.x & 63;
-  const int c = wend - base;
   const int Qw = (c + 63) >> 6, r = c - 64 * (Qw - 1);
   const int mine = lane < r ? Qw : Qw - 1;
-  const int next_has = (lane + 1 < r ? Qw : Qw - 1) > 0;
-  const int last = Qw > 1 ? 63 : r - 1;  // last lane holding entries
-  // row of the entry after this lane's last one (-1: the range ends there)
+  const int last = Qw > 1 ? 63 : r - 1;  // last lane holding entries (lanes 0..last do)
+  // row of the entry after this lane's last one, for lanes before `last`
+  unsigned pv[kQmax];
+  Val vv[kQmax];
+#pragma unroll
+  for (int q = 0; q < kQmax; ++q) {
+    pv[q] = ent_pk(e[q]);
+    vv[q] = ent_val(e[q]);
+  }
   const int frow = mine > 0 ? (int)(pv[0] >> 16) : -1;
-  const int nb = dpp32<kWaveShl1, 0xF, true>(frow);
-  int nrow = -1;
-  if (lane < 63 && next_has) nrow = nb;
-  else if (lane == last && wend < we) nrow = (int)(gload_nt(&pk[wend]) >> 16);
+  const int nrow = dpp32<kWaveShl1, 0xF, true>(frow);
+  const int frow0 = __builtin_amdgcn_readfirstlane(frow);
+  if (wr >= 0 && wr != frow0) {  // the carried run ended at the window boundary
+    if (lane == 0) lds_add(&s_acc[wr], wc);
+    wr = -1;
+  }
   int cur = -1, fr = 0;
   bool hend = false;
   Acc acc = Acc(0), fv = Acc(0);
@@ -152,7 +160,7 @@ __device__ __forceinline__ void sum_window(const unsigned* __restrict__ pk, int 
     acc = brk ? prods[q] : (act ? sum : acc);
     cur = act ? rr : cur;
   }
-  if (cur >= 0 && nrow != cur) {
+  if (lane < last && nrow != cur) {  // the lane's final run ends inside the window
     if (!hend) {
       hend = true;
       fr = cur;
@@ -162,7 +170,7 @@ __device__ __forceinline__ void sum_window(const unsigned* __restrict__ pk, int 
     }
     acc = Acc(0);
   }
-  if (lane == 0) {
+  if (lane == 0 && wr >= 0) {
     if (hend) fv = wc + fv;
     else acc = wc + acc;
   }
@@ -170,6 +178,13 @@ __device__ __forceinline__ void sum_window(const unsigned* __restrict__ pk, int 
   const Acc carry = wseg_excl<Acc>(hend ? 1 : 0, acc, out63);
   if (hend) lds_add(&s_acc[fr], fv + carry);
   wc = out63;
+  wr = __builtin_amdgcn_readlane(cur, last);
+}
+
+// Writes the run left open by a wave range's last window.
+template <class Acc>
+__device__ __forceinline__ void flush_open(Acc* s_acc, Acc wc, int wr) {
+  if (wr >= 0 && (threadIdx.x & 63) == 0) lds_add(&s_acc[wr], wc);
 }
 
 }  // namespace plss
