@@ -7,19 +7,20 @@
 // stripes of SW entries, staging each stripe's slice of x in LDS.  The
 // entries of a unit are grouped stripe by stripe and, inside a stripe, kept
 // in CSR order (row, then column); each entry packs its row inside the unit
-// and its column inside the stripe into one 32-bit word, so it still costs
-// 4 + value bytes.
+// and its column inside the stripe into one 32-bit word, stored with the
+// value as one record (12 bytes for float64, 8 for float32) that a lane
+// loads with one instruction.
 //
 // Inside a (unit, stripe) segment the 16 waves of the workgroup take 16
 // consecutive ranges of entries whose boundaries fall on row starts (fixed
 // when the store is built), so every row's stripe sum has exactly one
-// writer.  A wave walks its range in windows of at most 64*Q entries (Q <= 8
+// writer.  A wave walks its range in windows of at most 64*Q entries (Q <= 6
 // per lane, chosen from the range length): each lane takes a run of
 // consecutive entries, sums its runs of equal rows, and a wave-level
 // segmented scan (DPP row shifts and broadcasts) carries the open run from
 // lane to lane and from window to window.  Each window is stored
-// lane-interleaved (the lane's k-th entry at window start + 64 k + lane), so
-// every load instruction of the wave reads 64 consecutive entries.  Stripes
+// lane-interleaved (the lane's k-th record at window start + 64 k + lane), so
+// every load instruction of the wave reads 64 consecutive records.  Stripes
 // are applied in order, so each row sum has one fixed order: the product is
 // deterministic and does not depend on which other systems share a launch.
 // Wave bounds are read three stripes ahead and first windows two stripes
@@ -207,9 +208,15 @@ __global__ void k_st_interleave(const unsigned* __restrict__ pk, const Val* __re
 template <class Val, class Vin, class Acc, int MODE, int SW, int RB>
 __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const int2* __restrict__ list,
                                                int transposed) {
-  __shared__ Acc s_x[2][SW];
+  __shared__ __attribute__((aligned(16))) Acc s_x[2][SW];
   __shared__ Acc s_acc[RB];
   __shared__ double s_red[2][kSWaves];
+  // staging of the vector slice: XE elements per load, XC loads per thread.
+  // Float64 slices of four or more elements per thread go two to a load;
+  // wider loads measured slower for the narrower slices and for float32.
+  constexpr int XE = (sizeof(Vin) == 8 && SW / kST >= 4) ? 2 : 1;
+  constexpr int XC = SW / (kST * XE);
+  static_assert(XC * XE * kST == SW, "stripe width must be a multiple of the workgroup size");
 
   const int2 ent = list[blockIdx.x];
   if (ent.y < 0) return;  // padding of an XCD-interleaved list
@@ -277,12 +284,32 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
   __syncthreads();
 
   auto stripe = [&](int s, int& ws0, int& we0, const Ent<Val>* ce, int ws2, int we2, Ent<Val>* me) {
-    // the next stripe's slice of x travels in registers during this stripe
-    Acc nx[SW / kST];
+    // the next stripe's slice of x travels in registers during this stripe:
+    // chunk c of thread t holds elements c kST XE + t XE .. + XE - 1, one
+    // load each.  With XE > 1 a chunk that crosses the end of x loads the
+    // last XE elements of x instead and picks its own out of them by index
+    // (a vector shorter than XE is read from its start: every vector the
+    // products read sits in an allocation of at least 16 bytes), so every
+    // thread issues the same load without a branch.
+    Acc nx[XC][XE];
 #pragma unroll
-    for (int q = 0; q < SW / kST; ++q) {
-      const int j = (s + 1) * SW + q * kST + threadIdx.x;
-      nx[q] = (s + 1 < S && j < xlen) ? Acc(gload(&x[j])) : Acc(0);
+    for (int c = 0; c < XC; ++c) {
+      const int j0 = (s + 1) * SW + (c * kST + (int)threadIdx.x) * XE;
+      if constexpr (XE == 1) {
+        nx[c][0] = (s + 1 < S && j0 < xlen) ? Acc(gload(&x[j0])) : Acc(0);
+      } else {
+        const int jt = xlen > XE ? xlen - XE : 0;
+        const int jc = j0 + XE <= xlen ? j0 : jt;
+        const auto v = gload_vec<Vin, XE>(&x[jc]);
+#pragma unroll
+        for (int e = 0; e < XE; ++e) {
+          const int k = j0 + e - jc;  // in [0, XE) for every element below xlen
+          Vin pick = vec_elem(v, 0);
+#pragma unroll
+          for (int i = 1; i < XE; ++i) pick = k == i ? vec_elem(v, i) : pick;
+          nx[c][e] = (s + 1 < S && j0 + e < xlen) ? Acc(pick) : Acc(0);
+        }
+      }
     }
     int ws3, we3;
     bounds(s + 3, ws3, we3);
@@ -303,7 +330,9 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
       flush_open(s_acc, wc, wr);
     }
 #pragma unroll
-    for (int q = 0; q < SW / kST; ++q) s_x[(s + 1) & 1][q * kST + threadIdx.x] = nx[q];
+    for (int c = 0; c < XC; ++c)
+#pragma unroll
+      for (int e = 0; e < XE; ++e) s_x[(s + 1) & 1][(c * kST + threadIdx.x) * XE + e] = nx[c][e];
     ws0 = ws3;
     we0 = we3;
     __syncthreads();

@@ -75,6 +75,25 @@ __device__ __forceinline__ u32x3 gload_nt3(const unsigned* p) {
   using GP = const __attribute__((address_space(1))) u32x3*;
   return __builtin_nontemporal_load((GP)p);
 }
+// E consecutive elements of type T in one load (16 bytes at most; the
+// address needs only T's alignment)
+template <class T, int E> struct VecOf;
+template <> struct VecOf<double, 1> { typedef double type; };
+template <> struct VecOf<double, 2> { typedef double type __attribute__((ext_vector_type(2), aligned(8))); };
+template <> struct VecOf<float, 1> { typedef float type; };
+template <> struct VecOf<float, 2> { typedef float type __attribute__((ext_vector_type(2), aligned(4))); };
+template <> struct VecOf<float, 4> { typedef float type __attribute__((ext_vector_type(4), aligned(4))); };
+template <class T, int E>
+__device__ __forceinline__ typename VecOf<T, E>::type gload_vec(const T* p) {
+  using V = typename VecOf<T, E>::type;
+  using GP = const __attribute__((address_space(1))) V*;
+  return *(GP)p;
+}
+__device__ __forceinline__ double vec_elem(typename VecOf<double, 2>::type v, int i) { return v[i]; }
+__device__ __forceinline__ float vec_elem(typename VecOf<float, 2>::type v, int i) { return v[i]; }
+__device__ __forceinline__ float vec_elem(typename VecOf<float, 4>::type v, int i) { return v[i]; }
+__device__ __forceinline__ double vec_elem(double v, int) { return v; }
+__device__ __forceinline__ float vec_elem(float v, int) { return v; }
 template <class T>
 __device__ __forceinline__ void gstore(T* p, T v) {
   using GP = __attribute__((address_space(1))) T*;
