@@ -160,7 +160,11 @@ typedef struct {
   int32_t a_stripes;    /* products with A use the striped store */
   int32_t t_stripes;    /* products with Aᵀ use the striped row-block stores */
   int32_t unit_rows;    /* rows per unit, 1..16384 (at most 8192 are used for A);
-                           0 = chosen from the shape */
+                           0 = chosen from the shape, and for A the unit
+                           boundaries then moved so that the units hold about
+                           equal entry counts (as many units as at the chosen
+                           row count, at most 8192 rows each); reads back as
+                           that row count */
 } plss_layout;
 /* Read (got) and / or change (want) the layout of A; want = NULL only reads.
  * Building a striped store takes about (4 + value bytes) per entry of device

@@ -165,13 +165,54 @@ void fill_stripe_view(const PlssStripes& st, StripeView* v) {
   v->sw = st.sw;
 }
 
+// Row starts of the units of a striped store over CSR row pointers ptr.
+// Plain: units of R rows.  Balanced: at most ceil(rows / R) units of at most
+// cap rows (cap >= R) whose largest entry count is as small as a greedy
+// split can make it: the least bound T (binary search) for which cutting
+// each unit at the last row that keeps it within T entries (at least one
+// row, at most cap) needs no more units.  A launch ends with its heaviest
+// unit, so with rows of very different lengths equal row counts leave most
+// of the chip waiting for a few units.
+std::vector<int> unit_starts(const std::vector<int>& ptr, int rows, int R, int cap, bool balance) {
+  std::vector<int> st(1, 0);
+  if (rows <= 0) return st;
+  const int U = (rows + R - 1) / R;
+  if (!balance) {
+    for (int u = 1; u <= U; ++u) st.push_back((int)std::min<long long>(rows, (long long)u * R));
+    return st;
+  }
+  auto split = [&](long long T, std::vector<int>* out) {
+    int r = 0, u = 0;
+    while (r < rows && u <= U) {
+      const long long lim = (long long)ptr[r] + T;
+      int e = (int)(std::upper_bound(ptr.begin() + r, ptr.begin() + rows + 1, lim) - ptr.begin()) - 1;
+      e = std::min(std::max(e, r + 1), std::min(r + cap, rows));
+      r = e;
+      ++u;
+      if (out) out->push_back(r);
+    }
+    return r < rows ? U + 1 : u;
+  };
+  const long long total = ptr[rows] - ptr[0];
+  long long lo = (total + U - 1) / U, hi = std::max<long long>(lo, total);
+  while (lo < hi) {  // split(total) fits: units of cap >= R rows, at most U of them
+    const long long mid = lo + (hi - lo) / 2;
+    if (split(mid, nullptr) <= U) hi = mid;
+    else lo = mid + 1;
+  }
+  split(lo, &st);
+  return st;
+}
+
 // Striped copy of the CSR direction `src` restricted to columns
-// [colbase, colbase + ncols) (all of its entries lie there).
-static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, int sw, bool f32, PlssStripes& out,
-                          hipStream_t s) {
+// [colbase, colbase + ncols) (all of its entries lie there), in units of R
+// rows or (balance) units balanced by entry count of at most cap rows.
+static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, int cap, bool balance, int sw, bool f32,
+                          PlssStripes& out, hipStream_t s) {
   const int rows = src.nrows;
   const long long nnz = src.h_ptr[rows];
-  const int nunits = (rows + R - 1) / R;
+  const std::vector<int> urow = unit_starts(src.h_ptr, rows, R, cap, balance);
+  const int nunits = (int)urow.size() - 1;
   const int S = (ncols + sw - 1) / sw;
   if (S > kMaxStripes) throw InvalidArg{"too many columns for the striped layout"};
   const long long nseg = (long long)nunits * S;
@@ -183,8 +224,6 @@ static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, int
   unsigned* pk = nullptr;  // CSR-ordered entries of the segments, before the records
   void* val = nullptr;
   try {
-    std::vector<int> urow(nunits + 1);
-    for (int u = 0; u <= nunits; ++u) urow[u] = (int)std::min<long long>(rows, (long long)u * R);
     st.urow = static_cast<int*>(dmalloc(sizeof(int) * urow.size()));
     st.seg = static_cast<int*>(dmalloc(sizeof(int) * (size_t)(nseg + 1)));
     st.wsp = static_cast<int*>(dmalloc(sizeof(int) * (size_t)std::max<long long>(nseg * 16, 1)));
@@ -228,6 +267,7 @@ static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, int
   st.colbase = colbase;
   st.ncols = ncols;
   st.unit_rows = R;
+  st.balanced = balance;
   st.sw = sw;
   st.nnz = nnz;
   st.bytes = (size_t)(nnz + kStorePad) * (4 + vb) + sizeof(int) * (size_t)(nunits + 1 + (nseg + 1) + nseg * 16);
@@ -251,9 +291,10 @@ void matrix_set_layout(plss_matrix* M, bool a_stripes, bool t_stripes, int unit_
   try {
     if (a_stripes) {
       const int R = unit_rows ? std::min(unit_rows, kRBA) : auto_unit_rows(M->m, 1, kRBA);
-      if (!M->a_striped || M->SA.unit_rows != R) {
+      const bool bal = unit_rows == 0;
+      if (!M->a_striped || M->SA.unit_rows != R || M->SA.balanced != bal) {
         M->a_striped = false;
-        build_stripes(M->A, 0, (int)M->n, R, kSWA, M->f32, M->SA, s);
+        build_stripes(M->A, 0, (int)M->n, R, kRBA, bal, kSWA, M->f32, M->SA, s);
       }
     } else {
       free_stripes(M->SA);
@@ -262,10 +303,13 @@ void matrix_set_layout(plss_matrix* M, bool a_stripes, bool t_stripes, int unit_
     if (t_stripes) {
       build_row_blocks(M, s, true);
       const int R = unit_rows ? std::min(unit_rows, kRBT) : auto_unit_rows(M->n, M->nblk, kRBT);
-      if (!M->t_striped || M->SB[0].unit_rows != R) {
+      // the row blocks' units have near-equal entry counts already when
+      // their rows (columns of A) are; balancing them measured no faster
+      const bool bal = false;
+      if (!M->t_striped || M->SB[0].unit_rows != R || M->SB[0].balanced != bal) {
         M->t_striped = false;
         for (int b = 0; b < M->nblk; ++b)
-          build_stripes(M->TB[b], M->rb[b], M->rb[b + 1] - M->rb[b], R, kSWT, M->f32, M->SB[b], s);
+          build_stripes(M->TB[b], M->rb[b], M->rb[b + 1] - M->rb[b], R, kRBT, bal, kSWT, M->f32, M->SB[b], s);
       }
     } else {
       for (int b = 0; b < kMaxBlk; ++b) free_stripes(M->SB[b]);

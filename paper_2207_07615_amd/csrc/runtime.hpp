@@ -25,14 +25,15 @@ struct PlssDir {
   std::vector<int> h_ptr;  // host copy of ptr (tile construction)
 };
 
-// A striped store of one direction (stripe.hip): units of unit_rows rows,
-// stripes of sw columns of the gathered vector.
+// A striped store of one direction (stripe.hip): units of unit_rows rows (or
+// balanced by entry count), stripes of sw columns of the gathered vector.
 struct PlssStripes {
   unsigned* rec = nullptr; // nnz + kStorePad entry records (rec_words each)
   int* urow = nullptr;     // nunits + 1
   int* seg = nullptr;      // nunits * S + 1
   int* wsp = nullptr;      // nunits * S * 16
   int nunits = 0, S = 0, colbase = 0, ncols = 0, unit_rows = 0, sw = 0;
+  bool balanced = false;   // units balanced by entry count (at most ceil(rows / unit_rows) of them)
   long long nnz = 0;
   size_t bytes = 0;
 };
@@ -98,6 +99,7 @@ void matrix_set_layout(plss_matrix* M, bool a_stripes, bool t_stripes, int unit_
 // Layout chosen from the shape at creation.
 void auto_layout(long long m, long long n, long long nnz, bool f32, bool* a_stripes, bool* t_stripes);
 int auto_unit_rows(long long rows, int nblk, int rbmax);
+std::vector<int> unit_starts(const std::vector<int>& ptr, int rows, int R, int cap, bool balance);
 void fill_stripe_view(const PlssStripes& st, StripeView* v);
 
 }  // namespace plss
