@@ -147,7 +147,7 @@ plss_status plss_matrix_autotune(plss_handle* h, plss_matrix* A, int32_t* csr_wi
  *  - Stripes (1): a striped copy of the direction.  One workgroup owns a unit
  *    of rows and keeps their sums in LDS while the input vector passes
  *    through LDS in stripes; the entries of a unit are stored stripe by
- *    stripe.  Products with A: units of at most 8192 rows, stripes of 4096
+ *    stripe.  Products with A: units of at most 8192 rows, stripes of 6144
  *    entries.  For Aᵀ the rows of A are first split into 8 blocks (one per
  *    XCD) and each block gets its own striped store (units of at most 16384
  *    rows, stripes of 2048 entries); the block products are summed in block
@@ -172,7 +172,7 @@ typedef struct {
  * frees it.  plss_spmv and the residual-sketch solves use the layout in
  * force at the time of the call (the identity and mixed sketches always use
  * the tiles).  Errors: EINVAL for unit_rows outside [0, 16384] or more than
- * 8192 stripes (n above 33.5 million or m/8 above 16.7 million), ENOMEM; on error the
+ * 8192 stripes (n above 50.3 million or m/8 above 16.7 million), ENOMEM; on error the
  * directions whose store could not be built fall back to tiles. */
 plss_status plss_matrix_layout(plss_handle* h, plss_matrix* A, const plss_layout* want, plss_layout* got);
 

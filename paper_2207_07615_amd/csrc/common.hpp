@@ -41,12 +41,20 @@ constexpr int kMaxBlk = 8;         // row blocks of the transposed store (one pe
 
 // Striped store (stripe.hip): a work unit keeps its row sums in LDS while the
 // gathered vector passes through LDS in stripes; kSThreads threads per unit.
-// Stores of A: stripes of 4096 columns, units of at most 8192 rows.  Row-block
-// stores of Aᵀ: stripes of 2048, units of at most 16384 rows, so that the
-// product with Aᵀ runs one unit per CU (the same LDS, 2 x 16 KB + 128 KB).
-constexpr int kSWA = 4096, kRBA = 8192;
+// Stores of A: stripes of 6144 columns, units of at most 8192 rows (float64:
+// 2 x 48 KB of stripes + 64 KB of row sums, all of the 160 KB of LDS; fewer,
+// wider stripes cut the fixed cost per stripe).  Row-block stores of Aᵀ:
+// stripes of 2048, units of at most 16384 rows, so that the product with Aᵀ
+// runs one unit per CU (2 x 16 KB + 128 KB).  A stripe width need not be a
+// power of two: an entry keeps its column inside the stripe in 16 bits.
+constexpr int kSWA = 6144, kRBA = 8192;
 constexpr int kSWT = 2048, kRBT = 16384;
 constexpr int kSThreads = 1024;
+// most entries per lane in one window of a wave range (a window holds up to
+// 64 x this many entries); at the large shapes a wave's range in a stripe of
+// A averages about 410 entries, one of Aᵀ about 270.  Eight for A would need
+// more registers than a 1024-thread workgroup has.
+constexpr int kQmaxA = 7, kQmaxT = 6;
 constexpr int kMaxStripes = 8192;  // stripes per store (cursor table of the builder in LDS)
 constexpr size_t kSmallLds = 156 * 1024;  // LDS for r, p, y of a single-workgroup solve
 constexpr long long kSmallNnz = 1 << 18;  // automatic single-workgroup solves up to this many entries

@@ -57,7 +57,7 @@ void st_scatter(const int* ptr, const int* idx, const void* val, bool f32, int n
                 const int* d_seg, int S, int colbase, int sw, unsigned* opk, void* oval, hipStream_t s);
 void st_split(const unsigned* pk, const int* d_seg, long long nseg, int* d_wsp, hipStream_t s);
 void st_interleave(const unsigned* pk, const void* val, bool f32, const int* d_seg, const int* d_wsp, long long nseg,
-                   unsigned* rec, hipStream_t s);
+                   int qmax, unsigned* rec, hipStream_t s);
 void st_ysum(const double* ypart, int nblk, int n, double* y, hipStream_t s);
 void launch_sspmv(int mode, bool f32, const Desc* d, const int2* list, int n, int transposed, hipStream_t s);
 // exclusive scan of n counts into out[0..n] (work: (n + 1023) / 1024 + 1 long longs)

@@ -207,8 +207,8 @@ std::vector<int> unit_starts(const std::vector<int>& ptr, int rows, int R, int c
 // Striped copy of the CSR direction `src` restricted to columns
 // [colbase, colbase + ncols) (all of its entries lie there), in units of R
 // rows or (balance) units balanced by entry count of at most cap rows.
-static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, int cap, bool balance, int sw, bool f32,
-                          PlssStripes& out, hipStream_t s) {
+static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, int cap, bool balance, int sw, int qmax,
+                          bool f32, PlssStripes& out, hipStream_t s) {
   const int rows = src.nrows;
   const long long nnz = src.h_ptr[rows];
   const std::vector<int> urow = unit_starts(src.h_ptr, rows, R, cap, balance);
@@ -248,7 +248,7 @@ static void build_stripes(const PlssDir& src, int colbase, int ncols, int R, int
     const size_t words = (size_t)rec_words(f32);
     st.rec = static_cast<unsigned*>(dmalloc(sizeof(unsigned) * words * (size_t)(nnz + kStorePad)));
     PLSS_HIP(hipMemsetAsync(st.rec + words * (size_t)nnz, 0, sizeof(unsigned) * words * kStorePad, s));
-    st_interleave(pk, val, f32, st.seg, st.wsp, nseg, st.rec, s);
+    st_interleave(pk, val, f32, st.seg, st.wsp, nseg, qmax, st.rec, s);
     PLSS_HIP(hipStreamSynchronize(s));
   } catch (...) {
     dfree(cnt);
@@ -294,7 +294,7 @@ void matrix_set_layout(plss_matrix* M, bool a_stripes, bool t_stripes, int unit_
       const bool bal = unit_rows == 0;
       if (!M->a_striped || M->SA.unit_rows != R || M->SA.balanced != bal) {
         M->a_striped = false;
-        build_stripes(M->A, 0, (int)M->n, R, kRBA, bal, kSWA, M->f32, M->SA, s);
+        build_stripes(M->A, 0, (int)M->n, R, kRBA, bal, kSWA, kQmaxA, M->f32, M->SA, s);
       }
     } else {
       free_stripes(M->SA);
@@ -309,7 +309,8 @@ void matrix_set_layout(plss_matrix* M, bool a_stripes, bool t_stripes, int unit_
       if (!M->t_striped || M->SB[0].unit_rows != R || M->SB[0].balanced != bal) {
         M->t_striped = false;
         for (int b = 0; b < M->nblk; ++b)
-          build_stripes(M->TB[b], M->rb[b], M->rb[b + 1] - M->rb[b], R, kRBT, bal, kSWT, M->f32, M->SB[b], s);
+          build_stripes(M->TB[b], M->rb[b], M->rb[b + 1] - M->rb[b], R, kRBT, bal, kSWT, kQmaxT, M->f32, M->SB[b],
+                        s);
       }
     } else {
       for (int b = 0; b < kMaxBlk; ++b) free_stripes(M->SB[b]);

@@ -179,7 +179,7 @@ __device__ __forceinline__ void put_rec(unsigned* rec, long long i, unsigned pk,
 template <class Val>
 __global__ void k_st_interleave(const unsigned* __restrict__ pk, const Val* __restrict__ val,
                                 const int* __restrict__ seg, const int* __restrict__ wsp, long long nseg,
-                                unsigned* __restrict__ rec) {
+                                int qmax, unsigned* __restrict__ rec) {
   const int lane = threadIdx.x & 63;
   const long long nw = (long long)gridDim.x * (blockDim.x >> 6);
   for (long long q = (long long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < nseg * kSWaves; q += nw) {
@@ -187,7 +187,7 @@ __global__ void k_st_interleave(const unsigned* __restrict__ pk, const Val* __re
     const int w = (int)(q % kSWaves);
     const int ws = wsp[q], we = (w + 1 < kSWaves) ? wsp[q + 1] : seg[g + 1];
     if (we <= ws) continue;
-    const int Q = range_q(we - ws);
+    const int Q = range_q(we - ws, qmax);
     for (int base = ws; base < we; base += 64 * Q) {
       const int c = min(64 * Q, we - base);
       const int Qw = (c + 63) >> 6, r = c - 64 * (Qw - 1);
@@ -205,16 +205,18 @@ __global__ void k_st_interleave(const unsigned* __restrict__ pk, const Val* __re
 // unit list entry carries b << 24 | unit).  MODE_REFINE: r64 <- b - A x in
 // float64, partials of ||r64||^2 and ||b||^2.  MODE_PLAIN: r64 <- A p
 // (float64), or ypart[b] <- A_bᵀ p for a transposed store; no state.
-template <class Val, class Vin, class Acc, int MODE, int SW, int RB>
+template <class Val, class Vin, class Acc, int MODE, int SW, int RB, int QM>
 __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const int2* __restrict__ list,
                                                int transposed) {
   __shared__ __attribute__((aligned(16))) Acc s_x[2][SW];
   __shared__ Acc s_acc[RB];
-  __shared__ double s_red[2][kSWaves];
+  // the epilogue's cross-wave partial sums reuse the slice buffers (no wave
+  // reads them after the stripe loop's last barrier)
+  double (*s_red)[kSWaves] = reinterpret_cast<double (*)[kSWaves]>(&s_x[0][0]);
   // staging of the vector slice: XE elements per load, XC loads per thread.
   // Float64 slices of four or more elements per thread go two to a load;
   // wider loads measured slower for the narrower slices and for float32.
-  constexpr int XE = (sizeof(Vin) == 8 && SW / kST >= 4) ? 2 : 1;
+  constexpr int XE = (sizeof(Vin) == 8 && SW / kST >= 4 && (SW / kST) % 2 == 0) ? 2 : 1;
   constexpr int XC = SW / (kST * XE);
   static_assert(XC * XE * kST == SW, "stripe width must be a multiple of the workgroup size");
 
@@ -272,12 +274,12 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
   // cur's bounds then take stripe s + 3.  The loop is unrolled by three so
   // the sets keep fixed registers instead of being copied every stripe.
   int wsA, weA, wsB, weB, wsC, weC;
-  Ent<Val> eA[kQmax], eB[kQmax], eC[kQmax];
+  Ent<Val> eA[QM], eB[QM], eC[QM];
   bounds(0, wsA, weA);
   bounds(1, wsB, weB);
   bounds(2, wsC, weC);
-  load_window<Val>(rec, wsA, min(64 * range_q(weA - wsA), weA - wsA), eA);
-  load_window<Val>(rec, wsB, min(64 * range_q(weB - wsB), weB - wsB), eB);
+  load_window<Val, QM>(rec, wsA, min(64 * range_q(weA - wsA, QM), weA - wsA), eA);
+  load_window<Val, QM>(rec, wsB, min(64 * range_q(weB - wsB, QM), weB - wsB), eB);
 
   for (int i = threadIdx.x; i < nr; i += kST) s_acc[i] = Acc(0);
   for (int j = threadIdx.x; j < SW; j += kST) s_x[0][j] = j < xlen ? Acc(gload(&x[j])) : Acc(0);
@@ -313,19 +315,19 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
     }
     int ws3, we3;
     bounds(s + 3, ws3, we3);
-    load_window<Val>(rec, ws2, min(64 * range_q(we2 - ws2), we2 - ws2), me);
+    load_window<Val, QM>(rec, ws2, min(64 * range_q(we2 - ws2, QM), we2 - ws2), me);
 
     const Acc* __restrict__ xs = s_x[s & 1];
     if (we0 > ws0) {
-      const int Q = range_q(we0 - ws0);
+      const int Q = range_q(we0 - ws0, QM);
       Acc wc = Acc(0);  // run open at the end of the previous window
       int wr = -1;
-      sum_window<SW, Val, Acc>(min(64 * Q, we0 - ws0), ce, xs, s_acc, wc, wr);
+      sum_window<Val, Acc, QM>(min(64 * Q, we0 - ws0), ce, xs, s_acc, wc, wr);
       for (int base = ws0 + 64 * Q; base < we0; base += 64 * Q) {
         const int c = min(64 * Q, we0 - base);
-        Ent<Val> ev[kQmax];
-        load_window<Val>(rec, base, c, ev);
-        sum_window<SW, Val, Acc>(c, ev, xs, s_acc, wc, wr);
+        Ent<Val> ev[QM];
+        load_window<Val, QM>(rec, base, c, ev);
+        sum_window<Val, Acc, QM>(c, ev, xs, s_acc, wc, wr);
       }
       flush_open(s_acc, wc, wr);
     }
@@ -433,13 +435,14 @@ void st_split(const unsigned* pk, const int* d_seg, long long nseg, int* d_wsp, 
 }
 
 void st_interleave(const unsigned* pk, const void* val, bool f32, const int* d_seg, const int* d_wsp, long long nseg,
-                   unsigned* rec, hipStream_t s) {
+                   int qmax, unsigned* rec, hipStream_t s) {
   if (nseg <= 0) return;
   const int grid = st_grid(nseg * kSWaves * 64, 256);
   if (f32)
-    k_st_interleave<float><<<grid, 256, 0, s>>>(pk, static_cast<const float*>(val), d_seg, d_wsp, nseg, rec);
+    k_st_interleave<float><<<grid, 256, 0, s>>>(pk, static_cast<const float*>(val), d_seg, d_wsp, nseg, qmax, rec);
   else
-    k_st_interleave<double><<<grid, 256, 0, s>>>(pk, static_cast<const double*>(val), d_seg, d_wsp, nseg, rec);
+    k_st_interleave<double><<<grid, 256, 0, s>>>(pk, static_cast<const double*>(val), d_seg, d_wsp, nseg, qmax,
+                                                 rec);
   PLSS_HIP(hipGetLastError());
 }
 
@@ -450,25 +453,25 @@ void st_ysum(const double* ypart, int nblk, int n, double* y, hipStream_t s) {
 
 void launch_sspmv(int mode, bool f32, const Desc* d, const int2* list, int n, int transposed, hipStream_t s) {
   if (n <= 0) return;
-  constexpr int A1 = kSWA, A2 = kRBA, T1 = kSWT, T2 = kRBT;
+  constexpr int A1 = kSWA, A2 = kRBA, A3 = kQmaxA, T1 = kSWT, T2 = kRBT, T3 = kQmaxT;
   if (!f32) {
     switch (mode) {
-      case MODE_RESID: k_sspmv<double, double, double, MODE_RESID, A1, A2><<<n, kST, 0, s>>>(d, list, 0); break;
-      case MODE_TRANSB: k_sspmv<double, double, double, MODE_TRANSB, T1, T2><<<n, kST, 0, s>>>(d, list, 1); break;
-      case MODE_REFINE: k_sspmv<double, double, double, MODE_REFINE, A1, A2><<<n, kST, 0, s>>>(d, list, 0); break;
+      case MODE_RESID: k_sspmv<double, double, double, MODE_RESID, A1, A2, A3><<<n, kST, 0, s>>>(d, list, 0); break;
+      case MODE_TRANSB: k_sspmv<double, double, double, MODE_TRANSB, T1, T2, T3><<<n, kST, 0, s>>>(d, list, 1); break;
+      case MODE_REFINE: k_sspmv<double, double, double, MODE_REFINE, A1, A2, A3><<<n, kST, 0, s>>>(d, list, 0); break;
       default:
-        if (transposed) k_sspmv<double, double, double, MODE_PLAIN, T1, T2><<<n, kST, 0, s>>>(d, list, 1);
-        else k_sspmv<double, double, double, MODE_PLAIN, A1, A2><<<n, kST, 0, s>>>(d, list, 0);
+        if (transposed) k_sspmv<double, double, double, MODE_PLAIN, T1, T2, T3><<<n, kST, 0, s>>>(d, list, 1);
+        else k_sspmv<double, double, double, MODE_PLAIN, A1, A2, A3><<<n, kST, 0, s>>>(d, list, 0);
         break;
     }
   } else {
     switch (mode) {
-      case MODE_RESID: k_sspmv<float, float, float, MODE_RESID, A1, A2><<<n, kST, 0, s>>>(d, list, 0); break;
-      case MODE_TRANSB: k_sspmv<float, float, float, MODE_TRANSB, T1, T2><<<n, kST, 0, s>>>(d, list, 1); break;
-      case MODE_REFINE: k_sspmv<float, double, double, MODE_REFINE, A1, A2><<<n, kST, 0, s>>>(d, list, 0); break;
+      case MODE_RESID: k_sspmv<float, float, float, MODE_RESID, A1, A2, A3><<<n, kST, 0, s>>>(d, list, 0); break;
+      case MODE_TRANSB: k_sspmv<float, float, float, MODE_TRANSB, T1, T2, T3><<<n, kST, 0, s>>>(d, list, 1); break;
+      case MODE_REFINE: k_sspmv<float, double, double, MODE_REFINE, A1, A2, A3><<<n, kST, 0, s>>>(d, list, 0); break;
       default:
-        if (transposed) k_sspmv<float, double, double, MODE_PLAIN, T1, T2><<<n, kST, 0, s>>>(d, list, 1);
-        else k_sspmv<float, double, double, MODE_PLAIN, A1, A2><<<n, kST, 0, s>>>(d, list, 0);
+        if (transposed) k_sspmv<float, double, double, MODE_PLAIN, T1, T2, T3><<<n, kST, 0, s>>>(d, list, 1);
+        else k_sspmv<float, double, double, MODE_PLAIN, A1, A2, A3><<<n, kST, 0, s>>>(d, list, 0);
         break;
     }
   }

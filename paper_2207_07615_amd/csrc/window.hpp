@@ -2,7 +2,7 @@
 // single-workgroup kernels).
 //
 // A wave walks a row-aligned range of entries in windows of at most 64 * Q
-// entries (Q <= kQmax per lane).  In a window of c entries, lanes below
+// entries (Q <= QM per lane, QM fixed per store: QMA or QMT).  In a window of c entries, lanes below
 // r = c - 64 (Qw - 1) hold Qw = ceil(c / 64) consecutive entries (in CSR
 // order) and the others Qw - 1; the window is stored lane-interleaved, the
 // lane's k-th entry at window start + 64 k + lane.  Each entry is a packed
@@ -14,7 +14,6 @@
 
 namespace plss {
 
-constexpr int kQmax = 6;  // entries per lane of one window
 
 // Segmented scan over the 64 lanes of (f, v), where a set flag starts a new
 // segment after the element: incl_j = f_j ? v_j : incl_{j-1} + v_j.  Returns
@@ -62,9 +61,9 @@ __device__ __forceinline__ int win_count(int c, int lane) {
 }
 
 // wave range [ws, we): windows of 64 * Q entries, the last one shorter
-__device__ __forceinline__ int range_q(int len) {
+__host__ __device__ __forceinline__ int range_q(int len, int qmax) {
   const int Q = (len + 63) >> 6;
-  return Q > kQmax ? kQmax : (Q < 1 ? 1 : Q);
+  return Q > qmax ? qmax : (Q < 1 ? 1 : Q);
 }
 
 // One entry record in registers: (value, packed word) loaded by one
@@ -89,19 +88,19 @@ __device__ __forceinline__ float ent_val(u32x2 e) { return __builtin_bit_cast(fl
 // its end) and never uses it.  Double values: only the lane's own slots are
 // loaded (the uniform form needs more registers than the double kernel has
 // to spare).
-template <class Val>
+template <class Val, int QM>
 __device__ __forceinline__ void load_window(const unsigned* __restrict__ rec, int base, int c, Ent<Val>* e) {
   const int lane = threadIdx.x & 63;
   if constexpr (sizeof(Val) == 4) {
     const int Qw = (c + 63) >> 6;
     const unsigned* wp = rec + 2 * (size_t)(base + lane);
 #pragma unroll
-    for (int q = 0; q < kQmax; ++q) e[q] = q < Qw ? gload_nt2(wp + 128 * q) : u32x2{0u, 0xFFFFFFFFu};
+    for (int q = 0; q < QM; ++q) e[q] = q < Qw ? gload_nt2(wp + 128 * q) : u32x2{0u, 0xFFFFFFFFu};
   } else {
     const int mine = c > 0 ? win_count(c, lane) : 0;
     const unsigned* wp = rec + 3 * (size_t)(base + lane);
 #pragma unroll
-    for (int q = 0; q < kQmax; ++q) e[q] = q < mine ? gload_nt3(wp + 192 * q) : u32x3{0u, 0u, 0xFFFFFFFFu};
+    for (int q = 0; q < QM; ++q) e[q] = q < mine ? gload_nt3(wp + 192 * q) : u32x3{0u, 0u, 0xFFFFFFFFu};
   }
 }
 
@@ -113,7 +112,7 @@ __device__ __forceinline__ void load_window(const unsigned* __restrict__ rec, in
 // not; after the range's last window the caller writes it (flush_open).
 // No global load is needed to find where that run ends.  On entry wr = -1
 // if nothing is carried.
-template <int SW, class Val, class Acc>
+template <class Val, class Acc, int QM>
 __device__ __forceinline__ void sum_window(int c, const Ent<Val>* e, const Acc* __restrict__ xs, Acc* s_acc,
                                            Acc& wc, int& wr) {
   const int lane = threadIdx.x & 63;
@@ -121,10 +120,10 @@ __device__ __forceinline__ void sum_window(int c, const Ent<Val>* e, const Acc* 
   const int mine = lane < r ? Qw : Qw - 1;
   const int last = Qw > 1 ? 63 : r - 1;  // last lane holding entries (lanes 0..last do)
   // row of the entry after this lane's last one, for lanes before `last`
-  unsigned pv[kQmax];
-  Val vv[kQmax];
+  unsigned pv[QM];
+  Val vv[QM];
 #pragma unroll
-  for (int q = 0; q < kQmax; ++q) {
+  for (int q = 0; q < QM; ++q) {
     pv[q] = ent_pk(e[q]);
     vv[q] = ent_val(e[q]);
   }
@@ -140,13 +139,13 @@ __device__ __forceinline__ void sum_window(int c, const Ent<Val>* e, const Acc* 
   Acc acc = Acc(0), fv = Acc(0);
   // all gathers of the window first (back to back in LDS); a slot without an
   // entry reads a valid address and its product is never used
-  Acc prods[kQmax];
+  Acc prods[QM];
 #pragma unroll
-  for (int q = 0; q < kQmax; ++q) prods[q] = Acc(vv[q]) * xs[pv[q] & (SW - 1)];
+  for (int q = 0; q < QM; ++q) prods[q] = Acc(vv[q]) * xs[pv[q] & 0xFFFFu];
   // slots past the lane's entries leave the state unchanged (selects, so the
   // wave runs the slots without branching)
 #pragma unroll
-  for (int q = 0; q < kQmax; ++q) {
+  for (int q = 0; q < QM; ++q) {
     const bool act = q < mine;
     const int rr = (int)(pv[q] >> 16);
     const bool brk = act && rr != cur;
