@@ -52,8 +52,8 @@ constexpr int kSWT = 2048, kRBT = 16384;
 constexpr int kSThreads = 1024;
 // most entries per lane in one window of a wave range (a window holds up to
 // 64 x this many entries); at the large shapes a wave's range in a stripe of
-// A averages about 410 entries, one of Aᵀ about 270.  Eight for A would need
-// more registers than a 1024-thread workgroup has.
+// A averages about 410 entries, one of Aᵀ about 270 (eight for A measured
+// slower than seven, though fewer ranges then take a second window).
 constexpr int kQmaxA = 7, kQmaxT = 6;
 constexpr int kMaxStripes = 8192;  // stripes per store (cursor table of the builder in LDS)
 constexpr size_t kSmallLds = 156 * 1024;  // LDS for r, p, y of a single-workgroup solve

@@ -23,8 +23,8 @@
 // every load instruction of the wave reads 64 consecutive records.  Stripes
 // are applied in order, so each row sum has one fixed order: the product is
 // deterministic and does not depend on which other systems share a launch.
-// Wave bounds are read three stripes ahead and first windows two stripes
-// ahead, so their memory latency overlaps the arithmetic of the stripes in
+// Wave bounds are read two stripes ahead and first windows one stripe
+// ahead, so their memory latency overlaps the arithmetic of the stripe in
 // between.
 #include "kernels.hpp"
 #include "wave.hpp"
@@ -268,24 +268,22 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
       ws = we = 0;
     }
   };
-  // Three register sets rotate over the stripes: at stripe s, set "cur"
-  // holds stripe s (bounds and first window), the next set stripe s + 1, and
-  // the third receives stripe s + 2's first window while stripe s is summed;
-  // cur's bounds then take stripe s + 3.  The loop is unrolled by three so
-  // the sets keep fixed registers instead of being copied every stripe.
-  int wsA, weA, wsB, weB, wsC, weC;
-  Ent<Val> eA[QM], eB[QM], eC[QM];
+  // Two register sets alternate over the stripes: while stripe s is summed
+  // from set "cur" (bounds and first window), the other set receives stripe
+  // s + 1's first window (its bounds came a stripe earlier), and cur's
+  // bounds then take stripe s + 2.  The loop is unrolled by two so the sets
+  // keep fixed registers instead of being copied every stripe.
+  int wsA, weA, wsB, weB;
+  Ent<Val> eA[QM], eB[QM];
   bounds(0, wsA, weA);
   bounds(1, wsB, weB);
-  bounds(2, wsC, weC);
   load_window<Val, QM>(rec, wsA, min(64 * range_q(weA - wsA, QM), weA - wsA), eA);
-  load_window<Val, QM>(rec, wsB, min(64 * range_q(weB - wsB, QM), weB - wsB), eB);
 
   for (int i = threadIdx.x; i < nr; i += kST) s_acc[i] = Acc(0);
   for (int j = threadIdx.x; j < SW; j += kST) s_x[0][j] = j < xlen ? Acc(gload(&x[j])) : Acc(0);
   __syncthreads();
 
-  auto stripe = [&](int s, int& ws0, int& we0, const Ent<Val>* ce, int ws2, int we2, Ent<Val>* me) {
+  auto stripe = [&](int s, int& ws0, int& we0, const Ent<Val>* ce, int ws1, int we1, Ent<Val>* me) {
     // the next stripe's slice of x travels in registers during this stripe:
     // chunk c of thread t holds elements c kST XE + t XE .. + XE - 1, one
     // load each.  With XE > 1 a chunk that crosses the end of x loads the
@@ -313,9 +311,9 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
         }
       }
     }
-    int ws3, we3;
-    bounds(s + 3, ws3, we3);
-    load_window<Val, QM>(rec, ws2, min(64 * range_q(we2 - ws2, QM), we2 - ws2), me);
+    int ws2, we2;
+    bounds(s + 2, ws2, we2);
+    load_window<Val, QM>(rec, ws1, min(64 * range_q(we1 - ws1, QM), we1 - ws1), me);
 
     const Acc* __restrict__ xs = s_x[s & 1];
     if (we0 > ws0) {
@@ -335,16 +333,14 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
     for (int c = 0; c < XC; ++c)
 #pragma unroll
       for (int e = 0; e < XE; ++e) s_x[(s + 1) & 1][(c * kST + threadIdx.x) * XE + e] = nx[c][e];
-    ws0 = ws3;
-    we0 = we3;
+    ws0 = ws2;
+    we0 = we2;
     __syncthreads();
   };
-  for (int s = 0; s < S; s += 3) {
-    stripe(s, wsA, weA, eA, wsC, weC, eC);
+  for (int s = 0; s < S; s += 2) {
+    stripe(s, wsA, weA, eA, wsB, weB, eB);
     if (s + 1 >= S) break;
     stripe(s + 1, wsB, weB, eB, wsA, weA, eA);
-    if (s + 2 >= S) break;
-    stripe(s + 2, wsC, weC, eC, wsB, weB, eB);
   }
 
   // epilogue over the unit's rows
