@@ -23,7 +23,7 @@ plss_status run_group(plss_handle* h, const plss_matrix* A, int ncols, const dou
   while (W < ncols) W *= 2;
   const size_t vs = f32 ? 4 : 8;
   const int na_blk = (m + kRB - 1) / kRB, nt_blk = (n + kRB - 1) / kRB;
-  const int nu_blk = (int)(((long long)n * W + 4095) / 4096);
+  const int nu_blk = (int)(((long long)n * W + kUE - 1) / kUE);
   size_t off = 0;
   auto take = [&](size_t b) {
     size_t r = off;

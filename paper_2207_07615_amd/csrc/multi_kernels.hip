@@ -20,12 +20,13 @@ constexpr int kMW = 1024;  // threads of the per-block scalar kernel
 }  // namespace
 
 // Block product over the rows of one direction (CSR of A, or of Aᵀ).
-// W lanes per row (W >= s, a power of two), 256/W rows in flight per
-// workgroup, kRB rows per workgroup.  Per-column partial sums of the
+// W lanes per row (W >= s, a power of two), kMB/W rows in flight per
+// workgroup, kRB rows per workgroup (larger workgroups leave fewer per-block
+// partials for the one-workgroup scalar step to read).  Per-column partial sums of the
 // epilogue's squares go to part[blk * s + c] in a fixed order.
 template <class Val, class Vin, class Acc, int MODE, int W>
-__global__ __launch_bounds__(256) void k_spmm(const MDesc* __restrict__ d) {
-  constexpr int NS = 256 / W;
+__global__ __launch_bounds__(kMB) void k_spmm(const MDesc* __restrict__ d) {
+  constexpr int NS = kMB / W;
   __shared__ double s_p[2][NS][W];
   const MState* st = d->st;
   if (st->all_done) return;
@@ -50,7 +51,25 @@ __global__ __launch_bounds__(256) void k_spmm(const MDesc* __restrict__ d) {
     Acc acc = Acc(0);
     const int b0 = ptr[i], b1 = ptr[i + 1];
     if (col) {
-      for (int e = b0; e < b1; ++e) {
+      // eight entries at a time: their indices, values and gathered rows
+      // are all in flight before the first product (the sum keeps the
+      // entry order)
+      int e = b0;
+      for (; e + 8 <= b1; e += 8) {
+        int j[8];
+        Val v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          j[u] = idx[e + u];
+          v[u] = val[e + u];
+        }
+        Vin xv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) xv[u] = xin[(size_t)j[u] * s + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += Acc(v[u]) * Acc(xv[u]);
+      }
+      for (; e < b1; ++e) {
         const int j = idx[e];
         acc += Acc(val[e]) * Acc(xin[(size_t)j * s + c]);
       }
@@ -100,15 +119,25 @@ __device__ void col_sums(const double* __restrict__ part, int nb, int s, double*
   const int sub = threadIdx.x / s, c = threadIdx.x % s, nsub = kMW / s;
   double v = 0.0;
   if (sub < nsub) {
-    // 8 independent partial sums in flight, combined in a fixed order
-    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    int b = sub;
-    for (; b + 7 * nsub < nb; b += 8 * nsub) {
+    // 16 independent partial sums, their loads in flight together (one
+    // workgroup reads all the partials, so its loads in flight set the
+    // pace), combined in a fixed order
+    constexpr int U = 16;
+    double a[U];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] += part[(size_t)(b + u * nsub) * s + c];
+    for (int u = 0; u < U; ++u) a[u] = 0.0;
+    for (int b = sub; b < nb; b += U * nsub) {
+      double t[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) t[u] = b + u * nsub < nb ? part[(size_t)(b + u * nsub) * s + c] : 0.0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) a[u] += t[u];
     }
-    for (; b < nb; b += nsub) a[0] += part[(size_t)b * s + c];
-    v = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+#pragma unroll
+    for (int w = U / 2; w > 0; w >>= 1)
+#pragma unroll
+      for (int u = 0; u < w; ++u) a[u] = a[u] + a[u + w];
+    v = a[0];
   }
   __syncthreads();
   if (sub < nsub) s_tmp[sub * s + c] = v;
@@ -192,8 +221,8 @@ __global__ __launch_bounds__(kMW) void k_mstep(const MDesc* __restrict__ d) {
 
 // P <- beta P + gamma Y ; X <- X + P (X: inner solution) ; partial theta per column.
 template <class Vec>
-__global__ __launch_bounds__(256) void k_mupdate(const MDesc* __restrict__ d) {
-  __shared__ double s_p[256];
+__global__ __launch_bounds__(kMB) void k_mupdate(const MDesc* __restrict__ d) {
+  __shared__ double s_p[kMB];
   const MState* st = d->st;
   if (st->all_done) return;
   const int s = d->s;
@@ -201,16 +230,16 @@ __global__ __launch_bounds__(256) void k_mupdate(const MDesc* __restrict__ d) {
   Vec* P = static_cast<Vec*>(d->P);
   const Vec* Y = static_cast<const Vec*>(d->Y);
   double* X = d->Xi;
-  // 256 threads x 16 elements; s divides 256 (s a power of two here) so each
+  // kMB threads x 16 elements; s divides kMB (s a power of two here) so each
   // thread stays on one column
-  const long long base = (long long)blockIdx.x * 4096;
+  const long long base = (long long)blockIdx.x * kUE;
   const int c = threadIdx.x % s;
   double part = 0.0;
   if (!st->done[c]) {
     const double beta = st->beta[c], gamma = st->gamma[c];
     const bool fresh = st->fresh[c] != 0;
     for (int u = 0; u < 16; ++u) {
-      const long long o = base + (long long)u * 256 + threadIdx.x;
+      const long long o = base + (long long)u * kMB + threadIdx.x;
       if (o < total) {
         const double pn = fresh ? gamma * double(Y[o]) : beta * double(P[o]) + gamma * double(Y[o]);
         const Vec pv = Vec(pn);
@@ -224,7 +253,7 @@ __global__ __launch_bounds__(256) void k_mupdate(const MDesc* __restrict__ d) {
   __syncthreads();
   if (threadIdx.x < s) {
     double a = 0.0;
-    for (int q = threadIdx.x; q < 256; q += s) a += s_p[q];
+    for (int q = threadIdx.x; q < kMB; q += s) a += s_p[q];
     d->part_theta[(size_t)blockIdx.x * s + threadIdx.x] = a;
   }
 }
@@ -277,13 +306,13 @@ __global__ __launch_bounds__(kMW) void k_mouter(const MDesc* __restrict__ d) {
 
 // Inner start: R = C = R64 / nu (float32 storage) or R64, partial ||c||^2.
 template <class Vec>
-__global__ __launch_bounds__(256) void k_mstart(const MDesc* __restrict__ d) {
-  __shared__ double s_p[256];
+__global__ __launch_bounds__(kMB) void k_mstart(const MDesc* __restrict__ d) {
+  __shared__ double s_p[kMB];
   const MState* st = d->st;
   if (st->all_done) return;
   const int s = d->s;
   const int W = d->W;
-  const int NS = 256 / W, slot = threadIdx.x / W, c = threadIdx.x % W;
+  const int NS = kMB / W, slot = threadIdx.x / W, c = threadIdx.x % W;
   double part = 0.0;
   const bool live = c < s && !st->done[c] && st->k[c] == 0;
   const int row0 = blockIdx.x * kRB, row1 = min(row0 + kRB, d->m);
@@ -359,10 +388,10 @@ void launch_transpose_out(const double* src, int n, int ncols, int s, double* ds
 template <class Val, class Vin, class Acc, int MODE>
 static void spmm_w(int W, const MDesc* d, int grid, hipStream_t s) {
   switch (W) {
-    case 8: k_spmm<Val, Vin, Acc, MODE, 8><<<grid, 256, 0, s>>>(d); break;
-    case 16: k_spmm<Val, Vin, Acc, MODE, 16><<<grid, 256, 0, s>>>(d); break;
-    case 32: k_spmm<Val, Vin, Acc, MODE, 32><<<grid, 256, 0, s>>>(d); break;
-    case 64: k_spmm<Val, Vin, Acc, MODE, 64><<<grid, 256, 0, s>>>(d); break;
+    case 8: k_spmm<Val, Vin, Acc, MODE, 8><<<grid, kMB, 0, s>>>(d); break;
+    case 16: k_spmm<Val, Vin, Acc, MODE, 16><<<grid, kMB, 0, s>>>(d); break;
+    case 32: k_spmm<Val, Vin, Acc, MODE, 32><<<grid, kMB, 0, s>>>(d); break;
+    case 64: k_spmm<Val, Vin, Acc, MODE, 64><<<grid, kMB, 0, s>>>(d); break;
     default: throw InvalidArg{"bad block width"};
   }
 }
@@ -383,12 +412,12 @@ void launch_spmm(int mode, bool f32, int W, const MDesc* d, int grid, hipStream_
 void launch_mstep(const MDesc* d, hipStream_t s) { k_mstep<<<1, kMW, 0, s>>>(d); }
 void launch_mouter(const MDesc* d, hipStream_t s) { k_mouter<<<1, kMW, 0, s>>>(d); }
 void launch_mupdate(bool f32, const MDesc* d, int grid, hipStream_t s) {
-  if (f32) k_mupdate<float><<<grid, 256, 0, s>>>(d);
-  else k_mupdate<double><<<grid, 256, 0, s>>>(d);
+  if (f32) k_mupdate<float><<<grid, kMB, 0, s>>>(d);
+  else k_mupdate<double><<<grid, kMB, 0, s>>>(d);
 }
 void launch_mstart(bool f32, const MDesc* d, int grid, hipStream_t s) {
-  if (f32) k_mstart<float><<<grid, 256, 0, s>>>(d);
-  else k_mstart<double><<<grid, 256, 0, s>>>(d);
+  if (f32) k_mstart<float><<<grid, kMB, 0, s>>>(d);
+  else k_mstart<double><<<grid, kMB, 0, s>>>(d);
 }
 void launch_maxpy(const MDesc* d, int grid, hipStream_t s) { k_maxpy<<<grid, 256, 0, s>>>(d); }
 

@@ -5,7 +5,9 @@
 
 namespace plss {
 
-constexpr int kRB = 64;        // rows per workgroup of the block products
+constexpr int kMB = 1024;      // threads per workgroup of the block products and updates
+constexpr int kRB = 256;       // rows per workgroup of the block products (kMB / W in flight)
+constexpr int kUE = 16 * kMB;  // block elements per workgroup of the update
 constexpr int kMaxCols = 64;   // right-hand sides per block
 
 enum MMode : int { MMODE_RESID = 0, MMODE_TRANS = 1, MMODE_REFINE = 2 };
