@@ -252,12 +252,25 @@ __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
       Acc* sp = s_prod[w];
       int* so = s_off[w];
       for (int i = lane; i <= nr; i += 64) so[i] = ptr[r0 + i] - e0;
+      if (ne > 0) {
+        // all V index / value loads, then all V gathers, in flight together;
+        // slots past the tile's end reload its last entry and store nothing
+        int c[V];
+        Val v[V];
 #pragma unroll
-      for (int u = 0; u < V; ++u) {
-        const int e = u * 64 + lane;
-        if (e < ne)
-          sp[e] = Acc(__builtin_nontemporal_load(&val[e0 + e])) *
-                  Acc(xin[__builtin_nontemporal_load(&idx[e0 + e])]);
+        for (int u = 0; u < V; ++u) {
+          const int e = min(u * 64 + lane, ne - 1);
+          c[u] = __builtin_nontemporal_load(&idx[e0 + e]);
+          v[u] = __builtin_nontemporal_load(&val[e0 + e]);
+        }
+        Acc xv[V];
+#pragma unroll
+        for (int u = 0; u < V; ++u) xv[u] = Acc(xin[c[u]]);
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const int e = u * 64 + lane;
+          if (e < ne) sp[e] = Acc(v[u]) * xv[u];
+        }
       }
       wave_lds_sync();
       // each lane sums V consecutive products, split at row ends
