@@ -9,7 +9,9 @@ namespace plss {
 
 void* dmalloc(size_t bytes) {
   void* p = nullptr;
-  if (bytes == 0) bytes = 8;
+  // at least 16 bytes, in whole 16-byte units: the striped products read a
+  // vector shorter than one 16-byte load from its start
+  bytes = bytes == 0 ? 16 : (bytes + 15) / 16 * 16;
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();

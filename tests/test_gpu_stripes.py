@@ -50,6 +50,10 @@ CASES = {
     "zipf": (lambda: gen.large(m=60000, n=15000).A, 0),
     "one_unit": (lambda: gen.small(m=3000, n=1500).A, 8192),
     "big_t_units": (lambda: gen.tiny(6, 2000, 40000, 40).A, 16384),
+    # vectors shorter than one staging load (the product with A gathers from
+    # a vector of 1 or 3 entries; the transposed one scatters into it)
+    "one_col": (lambda: gen.make_csr(gen.rng_for(12), 5000, 1, np.ones(5000, dtype=np.int64), "normal"), 64),
+    "three_cols": (lambda: gen.make_csr(gen.rng_for(13), 7000, 3, np.full(7000, 2, dtype=np.int64), "normal"), 0),
 }
 
 
