@@ -26,26 +26,32 @@ constexpr int kSmT = 1024;         // threads per system
 constexpr int kSmWaves = kSmT / 64;
 constexpr int kLongRow = 64;       // rows longer than this are summed by a whole wave
 
-// Fixed-order workgroup sums of two values; the results are valid in every
-// thread.  s_red holds 2 x kSmWaves doubles.
-__device__ __forceinline__ void sm_sum2(double& a, double& b, double* s_red) {
+// Fixed-order workgroup sums of one value (TWO = false) or two; the results
+// are valid in every thread.  s_red holds two buffers of 2 x kSmWaves
+// doubles used in turn (par flips every call), so one barrier per call
+// suffices: a wave cannot write a buffer again before every wave has passed
+// the next call's barrier, which it reaches only after reading this call's
+// sums.  The barrier also publishes every LDS write made before the call.
+template <bool TWO>
+__device__ __forceinline__ void sm_sum2(double& a, double& b, double* s_red, int& par) {
   a = wave_sum_dpp(a);
-  b = wave_sum_dpp(b);
+  if (TWO) b = wave_sum_dpp(b);
   const int w = threadIdx.x >> 6;
-  __syncthreads();
+  double* buf = s_red + par * (2 * kSmWaves);
+  par ^= 1;
   if ((threadIdx.x & 63) == 0) {
-    s_red[w] = a;
-    s_red[kSmWaves + w] = b;
+    buf[w] = a;
+    if (TWO) buf[kSmWaves + w] = b;
   }
   __syncthreads();
-  double ta = s_red[0], tb = s_red[kSmWaves];
+  double ta = buf[0], tb = TWO ? buf[kSmWaves] : 0.0;
 #pragma unroll
   for (int q = 1; q < kSmWaves; ++q) {
-    ta += s_red[q];
-    tb += s_red[kSmWaves + q];
+    ta += buf[q];
+    if (TWO) tb += buf[kSmWaves + q];
   }
   a = ta;
-  b = tb;
+  if (TWO) b = tb;
 }
 
 // Row products of a CSR direction (row pointers in LDS): rows of at most
@@ -90,7 +96,8 @@ __device__ __forceinline__ void sm_rows(const int* __restrict__ ptr, const int* 
 template <class Val, class Vec>
 __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, const int* __restrict__ sys) {
   __shared__ double s_mem[kSmallLds / sizeof(double)];
-  __shared__ double s_red[2 * kSmWaves];
+  __shared__ double s_red[4 * kSmWaves];
+  int par = 0;  // buffer of the next workgroup sum
   const Desc* d = D + sys[blockIdx.x];
   State* st = d->st;
   const int m = d->m, n = d->n;
@@ -152,7 +159,7 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
       rr += ri * ri;
       bb += bi * bi;
     });
-    sm_sum2(rr, bb, s_red);
+    sm_sum2<true>(rr, bb, s_red, par);
     const double nu_new = sqrt(rr);
     if (outer == 0) nb_out = sqrt(bb);
     const double rel = (tol_abs || nb_out == 0.0) ? nu_new : nu_new / nb_out;
@@ -186,7 +193,7 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
       if (cvec) gstore(&cvec[i], ci);
       cc += double(ci) * double(ci);
     }
-    sm_sum2(cc, unused, s_red);  // its barrier also publishes r
+    sm_sum2<false>(cc, unused, s_red, par);  // its barrier also publishes r
     rho = cc;
     const double nb = sqrt(cc);
     if (f32) {
@@ -209,7 +216,7 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
           r[i] = rn;
           rp += double(rn) * double(rn);
         });
-        sm_sum2(rp, unused2, s_red);
+        sm_sum2<false>(rp, unused2, s_red, par);
         rho = rp;
       }
       if (threadIdx.x == 0 && k_total < hist_len) gstore(&hist[k_total], sqrt(rho) * scale);
@@ -227,7 +234,7 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
         const double ds = double(s);
         ph += wi ? ds * ds / gload(&wi[i]) : ds * ds;
       });
-      sm_sum2(ph, unused3, s_red);
+      sm_sum2<false>(ph, unused3, s_red, par);
       double beta, gamma;
       if (k == 0) {
         if (!(ph > 0.0)) {
@@ -257,7 +264,7 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
         xl[j] += double(pv);
         th += double(pv) * double(pv) * w;
       }
-      sm_sum2(th, unused4, s_red);
+      sm_sum2<false>(th, unused4, s_red, par);
       theta = th;
     }
     // the inner solution back to memory for the outer step
