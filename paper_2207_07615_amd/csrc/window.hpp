@@ -81,7 +81,8 @@ __device__ __forceinline__ float ent_val(u32x2 e) { return __builtin_bit_cast(fl
 
 // One lane-interleaved window of c entries into registers (the lane's
 // entries in CSR order), one record load per entry; a slot without an entry
-// holds row 0xFFFF, column 0xFFFF and value 0.  Float values: every lane
+// holds row 0xFFFF, column 0 and value 0 (its product reads a valid slot of
+// the slice and is never used).  Float values: every lane
 // loads all Qw = ceil(c / 64) slots, so the loads depend on wave-uniform
 // values only; a lane without an entry in the last slot reads one of the 63
 // records past the window (the store has kStorePad records of padding past
@@ -95,12 +96,12 @@ __device__ __forceinline__ void load_window(const unsigned* __restrict__ rec, in
     const int Qw = (c + 63) >> 6;
     const unsigned* wp = rec + 2 * (size_t)(base + lane);
 #pragma unroll
-    for (int q = 0; q < QM; ++q) e[q] = q < Qw ? gload_nt2(wp + 128 * q) : u32x2{0u, 0xFFFFFFFFu};
+    for (int q = 0; q < QM; ++q) e[q] = q < Qw ? gload_nt2(wp + 128 * q) : u32x2{0u, 0xFFFF0000u};
   } else {
     const int mine = c > 0 ? win_count(c, lane) : 0;
     const unsigned* wp = rec + 3 * (size_t)(base + lane);
 #pragma unroll
-    for (int q = 0; q < QM; ++q) e[q] = q < mine ? gload_nt3(wp + 192 * q) : u32x3{0u, 0u, 0xFFFFFFFFu};
+    for (int q = 0; q < QM; ++q) e[q] = q < mine ? gload_nt3(wp + 192 * q) : u32x3{0u, 0u, 0xFFFF0000u};
   }
 }
 
