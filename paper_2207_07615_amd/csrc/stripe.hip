@@ -14,7 +14,7 @@
 // Inside a (unit, stripe) segment the 16 waves of the workgroup take 16
 // consecutive ranges of entries whose boundaries fall on row starts (fixed
 // when the store is built), so every row's stripe sum has exactly one
-// writer.  A wave walks its range in windows of at most 64*Q entries (Q <= 6
+// writer.  A wave walks its range in windows of at most 64*Q entries (Q <= 7
 // per lane, chosen from the range length): each lane takes a run of
 // consecutive entries, sums its runs of equal rows, and a wave-level
 // segmented scan (DPP row shifts and broadcasts) carries the open run from

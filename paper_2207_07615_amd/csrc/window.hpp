@@ -1,12 +1,13 @@
-// Lane-interleaved windows of a striped store (shared by the striped and
-// single-workgroup kernels).
+// Lane-interleaved windows of a striped store (shared by the striped
+// product kernels).
 //
 // A wave walks a row-aligned range of entries in windows of at most 64 * Q
-// entries (Q <= QM per lane, QM fixed per store: QMA or QMT).  In a window of c entries, lanes below
-// r = c - 64 (Qw - 1) hold Qw = ceil(c / 64) consecutive entries (in CSR
-// order) and the others Qw - 1; the window is stored lane-interleaved, the
-// lane's k-th entry at window start + 64 k + lane.  Each entry is a packed
-// (row << 16 | column) word and a value.
+// entries (Q <= QM per lane; QM is fixed per store: kQmaxA for stores of A,
+// kQmaxT for the row-block stores of Aᵀ).  In a window of c entries, lanes
+// below r = c - 64 (Qw - 1) hold Qw = ceil(c / 64) consecutive entries (in
+// CSR order) and the others Qw - 1; the window is stored lane-interleaved,
+// the lane's k-th entry at window start + 64 k + lane.  Each entry is a
+// record of a value and a packed (row << 16 | column) word.
 #pragma once
 
 #include "common.hpp"
