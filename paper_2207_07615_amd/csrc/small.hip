@@ -24,7 +24,26 @@ namespace {
 
 constexpr int kSmT = 1024;         // threads per system
 constexpr int kSmWaves = kSmT / 64;
+static_assert(kSmWaves == 16, "the workgroup sums add one wave sum per lane of a 16-lane row");
 constexpr int kLongRow = 64;       // rows longer than this are summed by a whole wave
+
+// v of lane l (l wave-uniform); the result is uniform
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const long long b = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
+}
+
+// Inclusive sum over each row of 16 lanes (lane 15 of a row holds the row's
+// total), by DPP row shifts in a fixed order.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dppv<kRowShr1, 0xF, true>(v);
+  v += dppv<kRowShr2, 0xF, true>(v);
+  v += dppv<kRowShr4, 0xF, true>(v);
+  v += dppv<kRowShr8, 0xF, true>(v);
+  return v;
+}
 
 // Fixed-order workgroup sums of one value (TWO = false) or two; the results
 // are valid in every thread.  s_red holds two buffers of 2 x kSmWaves
@@ -44,14 +63,18 @@ __device__ __forceinline__ void sm_sum2(double& a, double& b, double* s_red, int
     if (TWO) buf[kSmWaves + w] = b;
   }
   __syncthreads();
-  double ta = buf[0], tb = TWO ? buf[kSmWaves] : 0.0;
-#pragma unroll
-  for (int q = 1; q < kSmWaves; ++q) {
-    ta += buf[q];
-    if (TWO) tb += buf[kSmWaves + q];
+  // lanes 0..15 of every wave read the 16 wave sums, one each, and add them
+  // within the first row of 16 lanes in a fixed order (shifts by 1, 2, 4, 8;
+  // lane 15 ends with the total)
+  const int l = threadIdx.x & 63;
+  double ta = l < kSmWaves ? buf[l] : 0.0;
+  double tb = TWO && l < kSmWaves ? buf[kSmWaves + l] : 0.0;
+  ta = row16_sum(ta);
+  a = lane_value(ta, kSmWaves - 1);
+  if (TWO) {
+    tb = row16_sum(tb);
+    b = lane_value(tb, kSmWaves - 1);
   }
-  a = ta;
-  if (TWO) b = tb;
 }
 
 // Row products of a CSR direction (row pointers in LDS): rows of at most
