@@ -10,8 +10,9 @@ resident in HBM (torch device tensors) during the timed region.
 Reported: PLSS iterations/s (value), solves/s, algorithmic HBM GB/s of the
 iteration, the roofline of the dominant kernel (per-kernel HIP events on
 the library's stream during the timed region), the oracle timed on the host
-on a bounded sample, and the float32-storage + float64-refinement arm of the
-same system (timed separately after the main region).
+on a bounded sample, and two more arms of the same system timed separately
+after the main region: float32 storage + float64 refinement, and PLSS W
+(W = diag(1/||A_{:,j}||), Section 4.1).
 
     python bench.py [--gpus 1] [--steps 10] [--warmup 2]
     python bench.py --config small|underdet|batch|multi|serve   (other workloads)
@@ -385,6 +386,7 @@ def main():
     ap.add_argument("--n", type=int, default=500_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 + refinement arm")
+    ap.add_argument("--no-w", action="store_true", help="skip the PLSS W arm (column-norm weights)")
     ap.add_argument("--autotune", action="store_true", help="pick tile widths by measurement")
     ap.add_argument("--layout", default="auto", choices=["auto", "tiles", "stripes"],
                     help="product layout of the large workload (auto: chosen from the shape)")
@@ -540,6 +542,29 @@ def main():
             "layout": M32.layout(),
         }
         del M32
+
+    if not args.no_w:
+        # PLSS W (Section 4.1): W = diag(1/||A_{:,j}||); the weights stream
+        # twice more per iteration (the block sum's phi and the update)
+        wi_h = np.sqrt(np.bincount(A.col_idx, weights=A.vals.astype(np.float64) ** 2, minlength=A.n))
+        wi = torch.from_numpy(np.where(wi_h > 0, wi_h, 1.0)).to(dev)
+        kww = dict(tol=1e-8, maxit=1000, wi=wi)
+        plss.solve(h, M, b, **kww)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        nw = max(1, args.steps // 2)
+        itsw = []
+        for _ in range(nw):
+            xw, iw, _ = plss.solve(h, M, b, **kww)
+            itsw.append(iw["iters"])
+        torch.cuda.synchronize()
+        ww = time.perf_counter() - t1
+        out["plss_w"] = {
+            "solves_per_s": nw / ww, "ms_per_solve": 1e3 * ww / nw,
+            "iters_per_solve": sum(itsw) / nw, "iters_per_s": sum(itsw) / ww,
+            "relres_true": iw["relres_true"], "status": iw["status_name"],
+            "solves_per_s_vs_plain": (nw / ww) / (args.steps / wall),
+        }
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sysm)

@@ -117,12 +117,16 @@ def test_zipf_rows_fp64_matches_oracle(h):
     assert info["relres_true"] <= 1.5e-8
 
 
-def test_weighted_W(h):
-    """PLSS W (Section 4.1): W = diag(1/||A_{:,j}||) through wi_diag."""
-    say("W")
+@pytest.mark.parametrize("engine", ["auto", "multi"])
+def test_weighted_W(h, engine):
+    """PLSS W (Section 4.1): W = diag(1/||A_{:,j}||) through wi_diag, in the
+    single-workgroup solver (auto at this size) and in the per-phase
+    launches (the block sum's phi and the update's p, theta weighted)."""
+    say("W", engine)
     sysm = gen.small(m=3000, n=1500)
     wi = np.sqrt(np.asarray(sysm.A.scipy().multiply(sysm.A.scipy()).sum(axis=0)).ravel())
-    fp64_parity(h, sysm, wi=wi)
+    kw = {} if engine == "auto" else {"engine": engine}
+    fp64_parity(h, sysm, wi=wi, **kw)
 
 
 def test_edge_cases(h):

@@ -125,6 +125,17 @@ def test_stripe_solve_matches_oracle(h, R):
     assert info["relres_true"] <= 1.5e-8
 
 
+def test_stripe_solve_weighted_W(h):
+    """PLSS W (Section 4.1) on the striped products: Zipf rows, 60000 x 15000,
+    W = diag(1/||A_{:,j}||) (column norms spread by the heavy rows)."""
+    say("stripe solve W")
+    sysm = gen.large(m=60000, n=15000)
+    S = sysm.A.scipy()
+    wi = np.sqrt(np.asarray(S.multiply(S).sum(axis=0)).ravel())
+    x, info, M = fp64_parity(h, sysm, wi=wi, layout={"a_stripes": True, "t_stripes": True})
+    assert info["relres_true"] <= 1.5e-8
+
+
 def test_stripe_solve_ragged_matches_oracle(h):
     """Underdetermined ragged system (empty rows, rows of 4500 entries), rows
     scaled to unit norm (with N(0,1) values the long rows make the system so
