@@ -210,11 +210,12 @@ def run_underdet(args):
     kw = dict(sketch="mixed", tol=1e-8, maxit=2000, row_perm=sysm.perm, hist_cap=128)
     for _ in range(args.warmup):
         plss.solve(h, M, sysm.b, **kw)
-    its = []
+    its, dev = [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         x, info, _ = plss.solve(h, M, sysm.b, **kw)
         its.append(info["iters"])
+        dev.append(info["ms"])
     wall = time.perf_counter() - t0
     t1 = time.perf_counter()
     ref = O.plss_columns(A, sysm.b, "mixed", perm=sysm.perm, tol=1e-300, maxit=8, hist_cap=128)
@@ -225,6 +226,7 @@ def run_underdet(args):
                                   "(residual + identity columns), FP64, tol 1e-8",
                       "m": A.m, "n": A.n, "nnz": A.nnz, "hist_cap": 128},
                      solves_per_s=args.steps / wall, updates_per_solve=sum(its) / len(its),
+                     device_ms_per_solve=sum(dev) / len(dev),
                      relres_true=info["relres_true"], status=info["status_name"],
                      rel_err_vs_oracle_8_updates=float(np.linalg.norm(x8 - ref.x) / np.linalg.norm(ref.x)),
                      cpu_baseline={"value": ref.iters / tc, "unit": "updates/s", "cores": 1, "kind": "oracle",

@@ -70,10 +70,13 @@ __global__ __launch_bounds__(kPW) void k_col_init(const Desc* __restrict__ D, co
   }
 }
 
-// w_l = (AP)ᵀ r, partial over a chunk of 1024 rows per workgroup:
-// part_w[l * wblk + blk] for l < kh.
-__global__ __launch_bounds__(kWG) void k_gemvt(const Desc* __restrict__ D, const int2* __restrict__ list) {
-  __shared__ double s_w[kWaves][256];
+// w_l = (AP)ᵀ r, partial over a chunk of 1024 rows per workgroup (one row
+// per thread, 16 waves): part_w[l * wblk + blk] for l < kh.  Four columns
+// of AP are read per pass, so 4 loads per thread are in flight; each wave
+// sums its 64 products per column, and the 16 wave sums are added in wave
+// order.
+__global__ __launch_bounds__(kPW) void k_gemvt(const Desc* __restrict__ D, const int2* __restrict__ list) {
+  __shared__ double s_w[kPW / 64][256];
   const int2 ent = list[blockIdx.x];
   const Desc* d = D + ent.x;
   const State* st = d->st;
@@ -82,28 +85,32 @@ __global__ __launch_bounds__(kWG) void k_gemvt(const Desc* __restrict__ D, const
   if (kh == 0) return;
   const int m = d->m, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int blk = ent.y;
-  const double* __restrict__ r = static_cast<const double*>(d->r);
-  double rv[4];
-  int ri[4];
+  const int ri = blk * 1024 + threadIdx.x;
+  const bool in = ri < m;
+  const double rv = in ? static_cast<const double*>(d->r)[ri] : 0.0;
+  const double* __restrict__ ap = d->AP + (in ? ri : 0);
+  int l = 0;
+  for (; l + 4 <= kh; l += 4) {
+    double a[4];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    ri[u] = blk * 1024 + u * kWG + threadIdx.x;
-    rv[u] = ri[u] < m ? r[ri[u]] : 0.0;
+    for (int k = 0; k < 4; ++k) a[k] = in ? ap[(size_t)(l + k) * m] * rv : 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a[k] = wsum(a[k]);
+    if (lane == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s_w[w][l + k] = a[k];
+    }
   }
-  for (int l = 0; l < kh; ++l) {
-    const double* __restrict__ ap = d->AP + (size_t)l * m;
-    double acc = 0.0;
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-      if (ri[u] < m) acc += ap[ri[u]] * rv[u];
-    acc = wsum(acc);
-    if (lane == 0) s_w[w][l] = acc;
+  for (; l < kh; ++l) {
+    double a = in ? ap[(size_t)l * m] * rv : 0.0;
+    a = wsum(a);
+    if (lane == 0) s_w[w][l] = a;
   }
   __syncthreads();
-  for (int l = threadIdx.x; l < kh; l += kWG) {
-    double a = s_w[0][l];
-    for (int q = 1; q < kWaves; ++q) a += s_w[q][l];
-    d->part_w[(size_t)l * d->wblk + blk] = a;
+  for (int q = threadIdx.x; q < kh; q += kPW) {
+    double a = s_w[0][q];
+    for (int v = 1; v < kPW / 64; ++v) a += s_w[v][q];
+    d->part_w[(size_t)q * d->wblk + blk] = a;
   }
 }
 
@@ -123,8 +130,18 @@ __global__ __launch_bounds__(kPW) void k_col_prep(const Desc* __restrict__ D, co
     // residual column: y = Aᵀ r (already in d->y), w = (AP)ᵀ r
     yy = bsum_array(d->part_phi, d->t_ntiles, s_red);
     if (l < kh) {
+      // the block partials in block order, eight loads in flight
       const double* pw = d->part_w + (size_t)l * d->wblk;
-      for (int b = 0; b < d->wblk; ++b) w += pw[b];
+      const int nb = d->wblk;
+      int b = 0;
+      for (; b + 8 <= nb; b += 8) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = pw[b + k];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) w += v[k];
+      }
+      for (; b < nb; ++b) w += pw[b];
     }
     sigma = st->rho;
   } else {
@@ -265,7 +282,7 @@ void launch_sketch_step(const Desc* d, int V, const int2* alist, int na, const i
                         bool residual_column, int VT, hipStream_t s) {
   if (residual_column) {
     launch_spmv(MODE_TRANS, false, VT, d, tlist, nt, 1, s);
-    k_gemvt<<<nw, kWG, 0, s>>>(d, wlist);
+    k_gemvt<<<nw, kPW, 0, s>>>(d, wlist);
   }
   k_col_prep<<<ns, kPW, 0, s>>>(d, sys);
   k_gemv<<<nu, kWG, 0, s>>>(d, ulist);
