@@ -265,10 +265,3 @@ def plss(A, b, sketch="residual", **kw) -> Result:
         kw.pop("hist_cap", None)
         return plss_residual(A, b, **kw)
     return plss_columns(A, b, sketch=sketch, **kw)
-
-
-def plss_refined_reference(A32_vals_as_f64_matrix, b, tol=1e-8, maxit=1000):
-    """The system a reduced-precision run solves is Â = fl32(A) itself (its
-    stored values widened to float64); the reference is Algorithm 1 on Â in
-    float64."""
-    return plss_residual(A32_vals_as_f64_matrix, b, tol=tol, maxit=maxit)
