@@ -952,8 +952,13 @@ __global__ __launch_bounds__(kWG) void k_ycomb(const Desc* __restrict__ D, const
   for (int u = 0; u < 4; ++u) {
     const int j = base + u * kWG + threadIdx.x;
     if (j < n) {
-      Vec s = yp[j];
-      for (int b = 1; b < nb; ++b) s += yp[(size_t)b * n + j];
+      // all blocks' partials loaded first, then added in block order
+      Vec v[kMaxBlk];
+#pragma unroll
+      for (int b = 0; b < kMaxBlk; ++b) v[b] = b < nb ? yp[(size_t)b * n + j] : Vec(0);
+      Vec s = v[0];
+#pragma unroll
+      for (int b = 1; b < kMaxBlk; ++b) s = b < nb ? s + v[b] : s;
       y[j] = s;
       const double ds = double(s);
       part += d->wi ? ds * ds / d->wi[j] : ds * ds;

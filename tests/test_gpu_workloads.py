@@ -112,3 +112,55 @@ def test_batch_workload(h):
         xa, ia, _ = plss.solve(h, mats[i], data[i][1], **kw)
         assert ia["iters"] == infos[i]["iters"]
         np.testing.assert_array_equal(xa, xs[i])
+
+
+def test_serve_workload(h):
+    """100 systems of the served stream (m log-uniform in [1e3, 1e6], n/m in
+    U(0.3, 1), Zipf rows, tolerance 1e-6 or 1e-10 each), float32 storage +
+    float64 refinement, all submitted at once as in the saturated run: every
+    request finishes; each converged one meets its own tolerance on the host;
+    two sampled results are bit-identical to the same system solved alone on
+    the per-phase engine the server runs."""
+    import time
+    import paper_2207_07615_amd as plss
+    say("serve workload: generating")
+    data = []
+    for s in gen.stream_systems(100):
+        A32 = s.A.astype(np.float32)
+        data.append((s, A32, gen.rhs(A32, s.xstar)))
+    srv = plss.Server(h, hbm_budget_bytes=200 << 30, max_slots=256)
+    kws = [dict(tol=s.tol, maxit=min(s.A.n + 1000, 4000), refine=True, inner_tol=1e-4) for s, _, _ in data]
+    say("serve workload: submitting")
+    reqs = [srv.submit(A32, b, storage="f32", **kw) for (_, A32, b), kw in zip(data, kws)]
+    out = {}
+    t0 = time.time()
+    while len(out) < len(reqs):
+        for i, r in enumerate(reqs):
+            if i not in out:
+                got = srv.poll(r)
+                if got is not None:
+                    out[i] = got
+        assert time.time() - t0 < 200, f"{len(out)} of {len(reqs)} finished"
+        time.sleep(0.002)
+    st = srv.stats()
+    srv.close()
+    assert st["submitted"] == st["finished"] == len(reqs)
+    ok = 0
+    for i, ((s, A32, b), kw) in enumerate(zip(data, kws)):
+        x, info = out[i]
+        assert np.all(np.isfinite(x))
+        if info["status"] == 0:
+            ok += 1
+            assert host_relres(A32, x, b) <= 1.5 * kw["tol"], (i, info)
+        else:
+            assert info["status"] in (1, 2), (i, info)
+    say("serve workload: converged", ok)
+    assert ok >= 60
+    sizes = np.argsort([s.A.m for s, _, _ in data])
+    for i in (int(sizes[0]), int(sizes[len(sizes) // 2])):
+        s, A32, b = data[i]
+        M = matrix(h, A32, "f32")
+        xa, ia, _ = plss.solve(h, M, b, engine="multi", **kws[i])
+        x, info = out[i]
+        assert ia["iters"] == info["iters"]
+        np.testing.assert_array_equal(xa, x)
