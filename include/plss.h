@@ -116,7 +116,11 @@ typedef struct plss_server plss_server;
  * refine on, inner_tol 1e-4, max_outer 20, everything else 0/NULL. */
 void plss_opts_default(plss_opts* opts);
 
-/* Create a handle on GPU `device` (its own non-blocking stream). */
+/* Create a handle on GPU `device` (its own non-blocking stream).  The calls
+ * on a handle are serialised and keep their device scratch on it between
+ * calls, growing it as needed: launch tables and per-system scalars, and for
+ * the identity and mixed sketches the history block of about
+ * 8 (m + n) hist_cap bytes.  plss_destroy frees it. */
 plss_status plss_create(plss_handle** h, int device);
 plss_status plss_destroy(plss_handle* h);
 

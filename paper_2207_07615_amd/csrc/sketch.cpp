@@ -56,7 +56,10 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
     const size_t oPw = off; off = up(off + 8 * (size_t)cap * wblk);
     const size_t oDn = off; off = up(off + 8 * (size_t)n);
     const size_t oPm = off; off = up(off + 4 * (size_t)m);
-    extra = static_cast<char*>(dmalloc(off));
+    // kept by the handle between calls (they are serialised by its mutex and
+    // synchronise before returning); nothing in it is read before this call
+    // writes it, except the dense row, cleared here
+    extra = workspace(h).hist_block(off);
     PLSS_HIP(hipMemsetAsync(extra + oDn, 0, 8 * (size_t)n, s));
     PLSS_HIP(hipMemcpyAsync(extra + oPm, perm.data(), 4 * (size_t)m, hipMemcpyHostToDevice, s));
     Desc d = run.desc;
@@ -141,14 +144,12 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
     info->status = fs.final_done ? fs.final_status : fs.status;
     info->ms = ms;
   } catch (...) {
-    dfree(extra);
     dfree(d_lists);
     dfree(d_state);
     dfree(d_desc);
     if (h_state) (void)hipHostFree(h_state);
     throw;
   }
-  dfree(extra);
   dfree(d_lists);
   dfree(d_state);
   dfree(d_desc);

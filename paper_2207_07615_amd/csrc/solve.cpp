@@ -210,9 +210,21 @@ char* Workspace::pin_block(size_t bytes) {
   return pin;
 }
 
+char* Workspace::hist_block(size_t bytes) {
+  if (bytes > hist_cap) {
+    dfree(hist);
+    hist = nullptr;
+    hist_cap = 0;
+    hist = static_cast<char*>(dmalloc(bytes));
+    hist_cap = bytes;
+  }
+  return hist;
+}
+
 Workspace::~Workspace() {
   if (aux) (void)hipStreamSynchronize(aux);
   dfree(dev);
+  dfree(hist);
   if (pin) (void)hipHostFree(pin);
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);

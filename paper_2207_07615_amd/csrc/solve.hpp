@@ -65,6 +65,8 @@ struct Workspace {
   size_t dev_cap = 0;
   char* pin = nullptr;
   size_t pin_cap = 0;
+  char* hist = nullptr;  // history block of the identity/mixed sketches (P, AP and their scratch)
+  size_t hist_cap = 0;
   ListSet lists;
   hipEvent_t t0 = nullptr, t1 = nullptr;
   hipEvent_t ready = nullptr, small_done = nullptr;
@@ -72,6 +74,7 @@ struct Workspace {
   std::vector<hipEvent_t> iter_events;  // 5 per timed iteration
   char* dev_block(size_t bytes);
   char* pin_block(size_t bytes);
+  char* hist_block(size_t bytes);
   ~Workspace();
 };
 Workspace& workspace(plss_handle* h);
