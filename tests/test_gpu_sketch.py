@@ -96,6 +96,33 @@ def test_history_cap_matches_oracle(h, cap):
     column_parity(h, sysm, "mixed", 1e-9, 3000, cap)
 
 
+def test_history_block_reuse_leaves_no_trace():
+    """A handle keeps the sketch history block between calls: a solve after
+    a larger one (block filled with its columns) and after a smaller one is
+    bit-identical to the same solve on a fresh handle."""
+    import paper_2207_07615_amd as plss
+    say("history block reuse")
+    big = gen.underdet(m=3000, n=12000)
+    mid = gen.tiny(43, 900, 2500, 12, "uniform")
+    small = gen.tiny(44, 60, 150, 8, "uniform")
+    kw = dict(sketch="mixed", tol=1e-10, maxit=400, hist_cap=48)
+
+    def solve(hd, sysm):
+        M = matrix(hd, sysm.A)
+        return plss.solve(hd, M, sysm.b, row_perm=sysm.perm, **kw)
+
+    fresh = plss.Handle(0)
+    x_ref, i_ref, _ = solve(fresh, mid)
+    reused = plss.Handle(0)
+    solve(reused, big)
+    x1, i1, _ = solve(reused, mid)
+    solve(reused, small)
+    x2, i2, _ = solve(reused, mid)
+    assert i1["iters"] == i2["iters"] == i_ref["iters"] > 0
+    np.testing.assert_array_equal(x1, x_ref)
+    np.testing.assert_array_equal(x2, x_ref)
+
+
 def test_mixed_underdetermined_medium(h):
     """The underdetermined recipe (30 nnz per row, U(-1,1)) at 20,000 x
     100,000, mixed sketch, tol 1e-8, against the oracle and A†b-consistency."""
