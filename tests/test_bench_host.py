@@ -41,3 +41,16 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_byte_model_per_iteration():
+    """The algorithmic bytes bench.py divides by the kernel times: per
+    iteration 24 nnz + 28 m + 60 n for float64 (the two products' 12 bytes
+    per entry, their row pointers and vector passes, and the update's five
+    vector passes), and 16 nnz + 16 m + 40 n for float32 storage, where x
+    stays float64 (16 n of the update's bytes)."""
+    bm = bench.bytes_model(M, N, NNZ)
+    assert bm["spmv"] == ALG_A and bm["spmvt"] == ALG_T
+    assert bm["iter"] == 24 * NNZ + 28 * M + 60 * N
+    b32 = bench.bytes_model(M, N, NNZ, f32=True)
+    assert b32["iter"] == 16 * NNZ + 16 * M + 40 * N
