@@ -85,10 +85,13 @@ def plss_residual_exact(A, b, maxit=None):
     return x, rs, ps
 
 
-def plss_columns_exact(A, b, columns):
+def plss_columns_exact(A, b, columns, used=None):
     """One-column sketch steps in rationals.  ``columns`` is a list of
-    ('r',) or ('e', i).  A column with sigma == 0 or delta == 0 is skipped.
-    Returns (x, residuals, updates)."""
+    ('r',) or ('e', i).  A column with sigma == 0 (the update would be zero)
+    or delta == 0 (y_k in the span of the stored updates, so appending it
+    would leave Y_k rank deficient, against eq. seqS) is skipped.  Returns
+    (x, residuals, updates); the columns that produced an update are appended
+    to ``used`` when given."""
     A = mat(A); b = vec(b)
     m, n = len(A), len(A[0])
     x = [Fraction(0)] * n
@@ -122,6 +125,8 @@ def plss_columns_exact(A, b, columns):
         x = axpy(Fraction(1), p, x)
         P.append(p); AP.append(Ap); Th.append(dot(p, p))
         rs.append(r); ps.append(p)
+        if used is not None:
+            used.append(tuple(col))
     return x, rs, ps
 
 

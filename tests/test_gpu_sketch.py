@@ -137,6 +137,95 @@ def test_mixed_underdetermined_medium(h):
     assert abs(full.iters - info["iters"]) <= 1
 
 
+def dependent_rows_system(seed=61):
+    """Identity-sketch system whose row order meets every branch of the skip
+    rule (Section 7, eq. pkKacz; reading C7): 20 row pairs (u, u) with u =
+    (1,1,1,1) on 4 own columns (dyadic, so the residual at the repeat is an
+    exact zero: sigma == 0); 20 triples (u, v, u + v) of N(0,1) rows on
+    disjoint supports (the sum is exact, the residual at it a rounding
+    remainder: delta ~ 1e-16 ||a||^2); 10 triples (w, z, w + z + 0.01 e_c)
+    (nearly dependent: an update); then 30 rows of 20 N(0,1) entries over all
+    columns, which overlap everything before them.  x* has entries in
+    {1, 2, 3}, so no row's right-hand side is zero by accident."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(seed)
+    n = 500
+    cols = list(rng.permutation(n))
+    rows = []
+    for _ in range(20):
+        c = [cols.pop() for _ in range(4)]
+        rows += [(c, [1.0] * 4)] * 2
+    for _ in range(20):
+        cu = [cols.pop() for _ in range(5)]
+        cv = [cols.pop() for _ in range(5)]
+        u, v = rng.standard_normal(5), rng.standard_normal(5)
+        rows += [(cu, list(u)), (cv, list(v)), (cu + cv, list(u) + list(v))]
+    for _ in range(10):
+        cw = [cols.pop() for _ in range(5)]
+        cz = [cols.pop() for _ in range(5)]
+        ce = [cols.pop()]
+        w, z = rng.standard_normal(5), rng.standard_normal(5)
+        rows += [(cw, list(w)), (cz, list(z)), (cw + cz + ce, list(w) + list(z) + [0.01])]
+    for _ in range(30):
+        c = list(rng.choice(n, 20, replace=False))
+        rows += [(c, list(rng.standard_normal(20)))]
+    m = len(rows)
+    D = np.zeros((m, n))
+    for i, (c, v) in enumerate(rows):
+        D[i, c] = v
+    xs = rng.integers(1, 4, n).astype(np.float64)
+    S = sp.csr_matrix(D)
+    S.sort_indices()
+    return D, S, S @ xs
+
+
+def test_identity_skip_rule_matches_oracle(h):
+    """Repeated, dependent and nearly dependent rows: the GPU skips the
+    columns the oracle skips (same update count, same number of columns
+    examined), its iterate after the pass agrees with the oracle's to 1e-10,
+    and it is A†b (Corollary 2 on the independent rows)."""
+    import paper_2207_07615_amd as plss
+    say("skip rule")
+    D, S, b = dependent_rows_system()
+    m, n = D.shape
+    M = plss.Matrix(h, S.indptr.astype(np.int64), S.indices.astype(np.int32), S.data, shape=(m, n))
+    order = np.arange(m, dtype=np.int32)
+    ref = O.plss_columns(D, b, "identity", perm=order, tol=1e-300, maxit=m, max_columns=m,
+                         record=True)
+    used = [c[1] for c in ref.columns]
+    skipped = sorted(set(range(m)) - set(used))
+    # the 20 repeats and the 20 exact sums, nothing else
+    assert len(skipped) == 40 and ref.iters == m - 40
+    x, info, _ = plss.solve(h, M, b, sketch="identity", tol=1e-300, maxit=ref.iters, row_perm=order)
+    err = rel(x, ref.x)
+    say(f"  updates={info['iters']} columns={info['outer_iters']} err={err:.3e}")
+    assert info["iters"] == ref.iters
+    assert info["outer_iters"] == m
+    assert err <= 1e-10
+    assert rel(x, pins.min_norm(D, b)) <= 1e-9
+    # converged solve: same updates as the oracle's own
+    x2, i2, _ = plss.solve(h, M, b, sketch="identity", tol=1e-12, maxit=10 * m, row_perm=order)
+    r2 = O.plss_columns(D, b, "identity", perm=order, tol=1e-12, maxit=10 * m)
+    assert i2["status"] == 0 and i2["iters"] == r2.iters
+    assert rel(x2, r2.x) <= 1e-10
+
+
+def test_mixed_skip_rule_matches_oracle(h):
+    """The same system under the mixed sketch: equal update counts and
+    iterates at every checked count."""
+    import paper_2207_07615_amd as plss
+    say("skip rule, mixed")
+    D, S, b = dependent_rows_system(seed=62)
+    m, n = D.shape
+    M = plss.Matrix(h, S.indptr.astype(np.int64), S.indices.astype(np.int32), S.data, shape=(m, n))
+    order = np.arange(m, dtype=np.int32)
+    for k in (10, 40, 90):
+        x, info, _ = plss.solve(h, M, b, sketch="mixed", tol=1e-300, maxit=k, row_perm=order)
+        ref = O.plss_columns(D, b, "mixed", perm=order, tol=1e-300, maxit=k)
+        assert info["iters"] == ref.iters == k
+        assert rel(x, ref.x) <= 1e-10, (k, rel(x, ref.x))
+
+
 def test_sketch_edge_cases(h):
     import paper_2207_07615_amd as plss
     say("sketch edges")

@@ -275,6 +275,99 @@ def test_identity_orthogonal_rows_equals_kaczmarz():
         np.testing.assert_allclose(res.xs[k + 1], kz[k], rtol=1e-13, atol=1e-14)
 
 
+# ---------------------------------------------------------------- skipped columns
+
+def _dependent_rows_system(eps=1e-3, seed=17):
+    """6 x 9 system whose identity columns hit every branch of the skip rule
+    (Section 7, eq. pkKacz; rank(S_k) = k of eq. seqS):
+      row 1 = row 0 (a repeated row),
+      row 3 = row 0 + row 2 (supports disjoint, so the float sum is exact),
+      row 5 = row 2 + row 4 + eps e_8 (nearly dependent: delta = eps^2 in
+      exact arithmetic, between 1e-14 and 1e-6 times ||a_5||^2).
+    Values are not dyadic, so the float residual at a dependent row is a
+    rounding remainder, not an exact zero."""
+    rng = np.random.default_rng(seed)
+    A = np.zeros((6, 9))
+    A[0, [0, 1]] = rng.standard_normal(2)
+    A[2, [2, 3, 4]] = rng.standard_normal(3)
+    A[4, [5, 6, 7]] = rng.standard_normal(3)
+    A[1] = A[0]
+    A[3] = A[0] + A[2]
+    A[5] = A[2] + A[4]
+    A[5, 8] = eps
+    xs = rng.standard_normal(9)
+    return A, A @ xs
+
+
+def test_identity_skip_rule_matches_exact_twin():
+    """The float oracle leaves out exactly the columns the rational run leaves
+    out: the repeated row and the exactly dependent row are skipped, the
+    nearly dependent row (delta/||a||^2 ~ 1e-11) is an update.  Skipped
+    columns are not counted, and one pass gives A†b (Corollary 2 on the
+    independent rows, whose constraints imply the others)."""
+    A, b = _dependent_rows_system()
+    ratio = 1e-6 / (A[5] @ A[5])            # delta / ||a_5||^2 of the last row
+    assert 1e-12 < ratio < 1e-6
+    used = []
+    xe, rs_e, ps_e = exact.plss_columns_exact(A, b, [("e", i) for i in range(6)], used=used)
+    assert used == [("e", 0), ("e", 2), ("e", 4), ("e", 5)]
+    res = O.plss_columns(A, b, "identity", perm=np.arange(6), tol=1e-300, maxit=6,
+                         max_columns=6, record=True)
+    assert [tuple(c) for c in res.columns] == used
+    assert res.iters == 4 and len(res.ps) == 4
+    # the float residual at rows 1 and 3 is not exactly zero when they are
+    # examined, so their skip is the delta branch of the rule
+    assert res.rs[1][1] != 0.0 or res.rs[2][3] != 0.0
+    # delta of the last row is a difference of two numbers of size ||a_5||^2
+    # that agree to ~6 digits, so ~1e-10 is what float64 leaves of it
+    x_exact = np.array([float(v) for v in xe])
+    assert np.linalg.norm(res.x - x_exact) <= 1e-8 * np.linalg.norm(x_exact)
+    xm = pins.min_norm(A[[0, 2, 4, 5]], b[[0, 2, 4, 5]])
+    assert np.linalg.norm(res.x - xm) <= 1e-8 * np.linalg.norm(xm)
+
+
+def test_identity_skip_rule_hand_worked_exact():
+    """Integer system with a repeated row and a dependent row, worked by hand:
+    x* = (1,2,3,4,5), rows a0 = (1,1,0,0,0), a1 = a0, a2 = (0,0,1,2,0),
+    a3 = a0 + a2, a4 = e_5; order 0,1,2,3,4.
+      col 0: sigma = 3, delta = 2, p = (3/2)(1,1,0,0,0)
+      col 1: r_1 = 0 -> skipped
+      col 2: sigma = 11, w = 0, delta = 5, p = (11/5)(0,0,1,2,0)
+      col 3: r_3 = 0 -> skipped
+      col 4: sigma = 5, delta = 1, p = 5 e_5, then r = 0.
+    Three updates, x = (3/2, 3/2, 11/5, 22/5, 5) = A†b."""
+    A = np.array([[1, 1, 0, 0, 0], [1, 1, 0, 0, 0], [0, 0, 1, 2, 0], [1, 1, 1, 2, 0],
+                  [0, 0, 0, 0, 1]], dtype=float)
+    b = A @ np.array([1, 2, 3, 4, 5], dtype=float)
+    used = []
+    x, rs, ps = exact.plss_columns_exact(A, b, [("e", i) for i in range(5)], used=used)
+    assert used == [("e", 0), ("e", 2), ("e", 4)]
+    F = Fraction
+    assert ps[0] == [F(3, 2), F(3, 2), 0, 0, 0]
+    assert ps[1] == [0, 0, F(11, 5), F(22, 5), 0]
+    assert ps[2] == [0, 0, 0, 0, F(5)]
+    assert x == [F(3, 2), F(3, 2), F(11, 5), F(22, 5), F(5)]
+    res = O.plss_columns(A, b, "identity", perm=np.arange(5), tol=1e-14, maxit=5, record=True)
+    assert res.status == O.OK and res.iters == 3
+    assert [tuple(c) for c in res.columns] == used
+    np.testing.assert_allclose(res.x, [1.5, 1.5, 2.2, 4.4, 5.0], rtol=1e-14)
+
+
+def test_mixed_skip_rule_matches_exact_twin():
+    """Mixed sketch on the dependent-rows system: the identity columns it
+    skips are those the rational run skips, and the update count agrees."""
+    A, b = _dependent_rows_system(seed=23)
+    cols = []
+    for i in range(6):
+        cols += [("r",), ("e", i)]
+    used = []
+    exact.plss_columns_exact(A, b, cols, used=used)
+    res = O.plss_columns(A, b, "mixed", perm=np.arange(6), tol=1e-300, maxit=len(used),
+                         max_columns=len(used) + 20, record=True)
+    assert [tuple(c) for c in res.columns][:len(used)] == used
+    assert res.iters == len(used)
+
+
 # ---------------------------------------------------------------- limits
 
 @pytest.mark.parametrize("m,n,L", [(20, 8, 4), (8, 20, 4), (64, 256, 30), (60, 60, 6)])
