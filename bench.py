@@ -71,23 +71,22 @@ def recorded_traffic(kernel_index, layout):
         return None
 
 
-def cpu_baseline(sysm, iters=60):
+def cpu_baseline(sysm, iters=60, threads=1):
     """The oracle (Algorithm 1 in float64, SciPy sparse products) on the
-    first `iters` iterations of the same system, single-threaded."""
-    try:
-        from threadpoolctl import threadpool_limits
-        lim = threadpool_limits(1)
-    except Exception:
-        lim = None
+    first `iters` iterations of the same system, with the host's thread
+    pools (BLAS / OpenMP) limited to `threads`.  SciPy's sparse products run
+    on one thread whatever the limit; only NumPy's dense dots use the pool."""
+    from threadpoolctl import threadpool_limits, threadpool_info
     from oracle import plss as O
-    t0 = time.perf_counter()
-    res = O.plss_residual(sysm.A, sysm.b, tol=1e-300, maxit=iters)
-    dt = time.perf_counter() - t0
-    if lim is not None:
-        lim.unregister() if hasattr(lim, "unregister") else None
-    return {"value": res.iters / dt, "unit": "iters/s", "cores": 1, "kind": "oracle",
+    with threadpool_limits(threads):
+        pool = max([p.get("num_threads", 1) for p in threadpool_info()] or [1])
+        t0 = time.perf_counter()
+        res = O.plss_residual(sysm.A, sysm.b, tol=1e-300, maxit=iters)
+        dt = time.perf_counter() - t0
+    return {"value": res.iters / dt, "unit": "iters/s", "cores": pool, "kind": "oracle",
             "sample": f"first {res.iters} iterations of the same float64 solve "
-                      f"({dt:.1f} s, SciPy CSR products, 1 thread)"}
+                      f"({dt:.1f} s, SciPy CSR products on one thread, NumPy dots on "
+                      f"{pool} thread{'s' if pool > 1 else ''})"}
 
 
 def _gen_batch(i):
@@ -233,44 +232,96 @@ def run_underdet(args):
                                    "sample": f"first {ref.iters} column steps ({tc:.1f} s)"})
 
 
+def host_relres(A, b, x):
+    """||b - A x|| / ||b|| on the host (SciPy, float64): the check every
+    counted solve must pass."""
+    import numpy as np
+    nb = float(np.linalg.norm(b))
+    r = float(np.linalg.norm(b - A.scipy() @ x))
+    return r / nb if nb > 0 else r
+
+
+def aggregate_roofline(byte_total, wall, what):
+    """Whole-run figure: algorithmic bytes of every iteration of every system
+    (bytes_model per inner iteration, plus one float64 residual pass per
+    outer step) over the wall time of the run."""
+    ach = byte_total / wall / 1e9 if wall > 0 else 0.0
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "kernel": what,
+            "algorithmic_bytes_total": byte_total, "wall_s": wall}
+
+
+def run_bytes(m, n, nnz, iters, outer, f32):
+    """Algorithmic bytes of one solve: its inner iterations plus, per outer
+    step, the refinement residual b - A x (matrix once, x, b and r64)."""
+    v = 4 if f32 else 8
+    return (iters * bytes_model(m, n, nnz, f32)["iter"] +
+            max(1, outer) * ((v + 4) * nnz + 4 * m + 8 * n + 16 * m))
+
+
 def run_batch(args):
     """256 uneven systems, FP32 storage + FP64 refinement to 1e-8, one launch
-    per phase over all unfinished systems."""
+    per phase over all unfinished systems.  Only systems that reach the
+    tolerance (status OK and the true residual checked on the host) count as
+    solves, in this arm and in the plain float64 baseline (every system
+    solved alone, matrices created before the timed loop as in the batch)."""
     import numpy as np
     import paper_2207_07615_amd as plss
     t0 = time.perf_counter()
     data = _pool_map(_gen_batch, range(args.nsys))
     log(f"generated {len(data)} systems in {time.perf_counter() - t0:.1f}s, "
         f"nnz total {sum(d[0].nnz for d in data)}")
+    tol = 1e-8
     h = plss.Handle(0)
     mats = [plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n), storage="f32") for A, _, _ in data]
     bs = [b for _, b, _ in data]
-    kw = dict(tol=1e-8, maxit=args.maxit_cap, refine=True, inner_tol=1e-4)
+    kw = dict(tol=tol, maxit=args.maxit_cap, refine=True, inner_tol=1e-4)
+    plss.solve_batch(h, mats[:8], bs[:8], **kw)   # warm-up (code objects, workspace)
     plss.kernel_times(h)
     t1 = time.perf_counter()
     xs, infos = plss.solve_batch(h, mats, bs, timing=True, **kw)
     wall = time.perf_counter() - t1
     kms, kn = plss.kernel_times(h)
-    ok = sum(1 for i in infos if i["status"] == 0)
-    errs = [float(np.linalg.norm(x - d[2]) / np.linalg.norm(d[2])) for x, d in zip(xs, data)]
+    rr = [host_relres(d[0], d[1], x) for x, d in zip(xs, data)]
+    ok = [i["status"] == 0 and r <= tol for i, r in zip(infos, rr)]
+    errs = [float(np.linalg.norm(x - d[2]) / np.linalg.norm(d[2])) for x, d, c in zip(xs, data, ok) if c]
     tot_nnz = sum(d[0].nnz for d in data)
-    # one system at a time, plain float64 Algorithm 1, same GPU (baseline)
-    sub = list(range(0, len(data), max(1, len(data) // 16)))
+    byte_total = sum(run_bytes(d[0].m, d[0].n, d[0].nnz, i["iters"], i["outer_iters"], True)
+                     for d, i in zip(data, infos))
+    # the same batch after the library's autotuner picked each matrix's tile
+    # widths by timing its plain products (per matrix, per direction)
+    t_tune = time.perf_counter()
+    tiles = [M.autotune() for M in mats]
+    t_tune = time.perf_counter() - t_tune
+    t1 = time.perf_counter()
+    xs_t, infos_t = plss.solve_batch(h, mats, bs, **kw)
+    wall_t = time.perf_counter() - t1
+    ok_t = sum(1 for x, i, d in zip(xs_t, infos_t, data) if i["status"] == 0 and host_relres(d[0], d[1], x) <= tol)
+    del mats
+    # one system at a time, plain float64 Algorithm 1 on the same GPU
+    m64 = [plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n)) for A, _, _ in data]
+    plss.solve(h, m64[0], bs[0], tol=tol, maxit=args.maxit_cap)
     t2 = time.perf_counter()
-    for i in sub:
-        A, b, xs_ = data[i]
-        M64 = plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n))
-        plss.solve(h, M64, b, tol=1e-8, maxit=args.maxit_cap)
-        del M64
-    t_plain = (time.perf_counter() - t2) / len(sub) * len(data)
-    return base_line(METRIC, len(data) / wall, "solves/s", 1, 0, wall, "f32+f64",
+    res64 = [plss.solve(h, M64, b, tol=tol, maxit=args.maxit_cap)[:2] for M64, b in zip(m64, bs)]
+    t_plain = time.perf_counter() - t2
+    ok64 = [i["status"] == 0 and host_relres(d[0], d[1], x) <= tol for (x, i), d in zip(res64, data)]
+    del m64
+    nok, nok64 = sum(ok), sum(ok64)
+    return base_line(METRIC, nok / wall, "solves/s", 1, 0, wall, "f32+f64",
                      {"workload": f"batch: {len(data)} systems, m log-U[1e3,2e5], n=m*U(.5,1), 5-50 nnz/row, "
                                   "FP32 storage + FP64 refinement, tol 1e-8", "nnz_total": tot_nnz,
-                      "maxit": args.maxit_cap},
-                     converged=ok, max_rel_err_vs_xstar=max(errs),
+                      "maxit": args.maxit_cap, "tiles": "default widths (autotuned run below)"},
+                     counted="solves with status OK and host-checked ||b - A x||/||b|| <= tol",
+                     converged=nok, systems=len(data), max_rel_err_vs_xstar=max(errs) if errs else None,
                      iters_total=sum(i["iters"] for i in infos),
                      kernel_ms_total=dict(zip(["spmv", "spmvt", "step", "update"], kms)),
-                     plain_fp64_one_at_a_time_s=t_plain, speedup_vs_plain_fp64=t_plain / wall)
+                     roofline=aggregate_roofline(byte_total, wall, "whole batch (all phases)"),
+                     plain_fp64={"solves_per_s": nok64 / t_plain, "converged": nok64, "wall_s": t_plain,
+                                 "how": "every system alone, float64 storage, same GPU"},
+                     speedup_vs_plain_fp64=(nok / wall) / (nok64 / t_plain) if nok64 else None,
+                     autotuned={"solves_per_s": ok_t / wall_t, "converged": ok_t, "wall_s": wall_t,
+                                "tune_s": t_tune, "widths_a_t": {f"{a},{t}": tiles.count((a, t))
+                                                                 for a, t in sorted(set(tiles))}})
 
 
 def run_multi(args):
@@ -317,7 +368,9 @@ def run_multi(args):
 
 def run_serve(args):
     """Served stream: systems with Poisson arrivals, FP32 storage + FP64
-    refinement under continuous batching, against plain per-system FP64."""
+    refinement under continuous batching, against plain per-system FP64.
+    Only requests that reach their own tolerance (status OK and the true
+    residual checked on the host) count as solves, in both arms."""
     import numpy as np
     import paper_2207_07615_amd as plss
     import plss_inputs as gen
@@ -327,6 +380,9 @@ def run_serve(args):
     h = plss.Handle(0)
     budget = 200 << 30
 
+    def cap(s):
+        return min(s.A.n + 1000, args.maxit_cap)
+
     def serve(arrivals):
         srv = plss.Server(h, hbm_budget_bytes=budget, max_slots=256)
         t_start = time.perf_counter()
@@ -334,9 +390,8 @@ def run_serve(args):
         for (s, A32, b32), ta in zip(data, arrivals):
             while time.perf_counter() - t_start < ta:
                 time.sleep(0.0005)
-            reqs.append(srv.submit(A32, b32, storage="f32", tol=s.tol,
-                                   maxit=min(s.A.n + 1000, args.maxit_cap), refine=True, inner_tol=1e-4))
-        res = []
+            reqs.append(srv.submit(A32, b32, storage="f32", tol=s.tol, maxit=cap(s),
+                                   refine=True, inner_tol=1e-4))
         pending = list(range(len(reqs)))
         got = {}
         while pending:
@@ -353,30 +408,61 @@ def run_serve(args):
         srv.close()
         return wall, [got[i] for i in range(len(reqs))]
 
+    def counted(res, which):
+        out = []
+        for (s, A32, b32), (x, info) in zip(data, res):
+            A, b = (A32, b32) if which == "f32" else (s.A, s.b)
+            out.append(info["status"] == 0 and host_relres(A, b, x) <= s.tol)
+        return out
+
+    def by_tol(flags):
+        return {f"{t:g}": [sum(1 for (s, _, _), f in zip(data, flags) if s.tol == t and f),
+                           sum(1 for s, _, _ in data if s.tol == t)] for t in (1e-6, 1e-10)}
+
+    def pct(v, q):
+        v = sorted(v)
+        return v[min(len(v) - 1, max(0, int(math.ceil(q * len(v))) - 1))] if v else None
+
     n = len(data)
+    serve([0.0] * min(n, 8))                     # warm-up (code objects, workspace)
     wall_sat, res_sat = serve([0.0] * n)
-    rate = 0.7 * n / wall_sat
+    ok_sat = counted(res_sat, "f32")
+    rate = 0.7 * sum(ok_sat) / wall_sat
     arr = gen.poisson_arrivals(n, rate)
     wall_p, res_p = serve(list(arr))
-    lat = sorted(info["ms"] for _, info in res_p)
-    conv = sum(1 for _, info in res_sat if info["status"] == 0)
-    # plain per-system FP64 Algorithm 1 on the same GPU, one at a time
+    ok_p = counted(res_p, "f32")
+    lat_ok = [info["ms"] for (_, info), f in zip(res_p, ok_p) if f]
+    lat_all = [info["ms"] for _, info in res_p]
+    byte_total = sum(run_bytes(s.A.m, s.A.n, s.A.nnz, info["iters"], info["outer_iters"], True)
+                     for (s, _, _), (_, info) in zip(data, res_sat))
+    # plain per-system FP64 Algorithm 1 on the same GPU, one request at a time
+    # (each request brings its matrix: upload and transpose are timed, as in
+    # the served arm)
     t1 = time.perf_counter()
+    res64 = []
     for s, _, _ in data:
         M64 = plss.Matrix(h, s.A.row_ptr, s.A.col_idx, s.A.vals, shape=(s.A.m, s.A.n))
-        plss.solve(h, M64, s.b, tol=s.tol, maxit=min(s.A.n + 1000, args.maxit_cap))
+        res64.append(plss.solve(h, M64, s.b, tol=s.tol, maxit=cap(s))[:2])
         del M64
     t_plain = time.perf_counter() - t1
-    return base_line(METRIC, n / wall_sat, "solves/s", 1, 0, wall_sat, "f32+f64",
+    ok64 = counted(res64, "f64")
+    nsat, n64 = sum(ok_sat), sum(ok64)
+    return base_line(METRIC, nsat / wall_sat, "solves/s", 1, 0, wall_sat, "f32+f64",
                      {"workload": f"serve: {n} systems of the stream recipe (m log-U[1e3,1e6], n/m U(.3,1), "
                                   "Zipf(1.5) rows clipped to [1,100], tol 1e-6 or 1e-10), FP32 + FP64 refinement, "
                                   "continuous batching", "nnz_total": sum(s.A.nnz for s, _, _ in data),
                       "maxit": f"min(n + 1000, {args.maxit_cap})"},
-                     saturated_solves_per_s=n / wall_sat, poisson_rate=rate,
-                     poisson_solves_per_s=n / wall_p, p50_ms=lat[len(lat) // 2],
-                     p99_ms=lat[min(len(lat) - 1, int(math.ceil(0.99 * len(lat))) - 1)],
-                     converged=conv, plain_fp64_solves_per_s=n / t_plain,
-                     speedup_vs_plain_fp64=(n / wall_sat) / (n / t_plain))
+                     counted="requests with status OK and host-checked ||b - A x||/||b|| <= their tol",
+                     systems=n, converged=nsat, converged_by_tol=by_tol(ok_sat),
+                     saturated_solves_per_s=nsat / wall_sat, poisson_rate=rate,
+                     poisson_solves_per_s=sum(ok_p) / wall_p, poisson_converged=sum(ok_p),
+                     p50_ms=pct(lat_ok, 0.5), p99_ms=pct(lat_ok, 0.99),
+                     p50_ms_all_requests=pct(lat_all, 0.5), p99_ms_all_requests=pct(lat_all, 0.99),
+                     roofline=aggregate_roofline(byte_total, wall_sat, "whole saturated run (all phases)"),
+                     plain_fp64={"solves_per_s": n64 / t_plain, "converged": n64, "wall_s": t_plain,
+                                 "converged_by_tol": by_tol(ok64),
+                                 "how": "every request alone (matrix upload + solve), float64, same GPU"},
+                     speedup_vs_plain_fp64=(nsat / wall_sat) / (n64 / t_plain) if n64 else None)
 
 
 def main():
@@ -396,7 +482,7 @@ def main():
                     help="also run a 1 GiB device copy (calibrates profiler byte counters)")
     ap.add_argument("--config", default="large",
                     choices=["large", "small", "underdet", "batch", "multi", "serve"])
-    ap.add_argument("--nsys", type=int, default=0, help="systems for batch/serve (default 256 / 100)")
+    ap.add_argument("--nsys", type=int, default=0, help="systems for batch/serve (default 256 / 200)")
     ap.add_argument("--maxit-cap", type=int, default=4000,
                     help="batch/serve: iteration bound min(n + 1000, cap) per system")
     args = ap.parse_args()
@@ -406,7 +492,7 @@ def main():
         sys.exit(2)
     if args.config != "large":
         if not args.nsys:
-            args.nsys = 256 if args.config == "batch" else 100
+            args.nsys = 256 if args.config == "batch" else 200
         fn = {"small": run_small, "underdet": run_underdet, "batch": run_batch,
               "multi": run_multi, "serve": run_serve}[args.config]
         print(json.dumps(fn(args)), flush=True)
@@ -570,6 +656,8 @@ def main():
 
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(sysm)
+        # the same oracle with every host thread pool at the machine's CPU share
+        out["cpu_baseline_all_cores"] = cpu_baseline(sysm, iters=40, threads=min(16, os.cpu_count() or 1))
 
     print(json.dumps(out), flush=True)
 

@@ -13,7 +13,7 @@ import pytest
 import plss_inputs as gen
 from oracle import plss as O
 
-from gpu_common import fp64_parity, matrix, order_spread, rel
+from gpu_common import CONVERGED_TOL, converged_check, fp64_parity, matrix, order_bound, order_spread, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -58,7 +58,7 @@ def test_small_engine_small_workload(h):
     """2000 x 1000, 8 entries per row, FP64, tol 1e-8: the oracle protocol."""
     say("single engine: small workload")
     sysm = gen.small()
-    x, info, M = fp64_parity(h, sysm, engine="single")
+    x, info, M = fp64_parity(h, sysm, engine="single", case="small_single_engine")
     assert info["relres_true"] <= 1.5e-8
 
 
@@ -87,8 +87,15 @@ def test_engines_agree(h, case):
     ref, spread = order_spread(sysm.A, sysm.b, k, wi=wi)
     xs_k, _, _ = plss.solve(h, M, sysm.b, tol=1e-300, maxit=k, wi=wi, engine="single")
     xm_k, _, _ = plss.solve(h, M, sysm.b, tol=1e-300, maxit=k, wi=wi, engine="multi")
-    assert rel(xs_k, ref.x) <= max(1e-10, 4 * spread)
-    assert rel(xm_k, ref.x) <= max(1e-10, 4 * spread)
+    order_bound(rel(xs_k, ref.x), spread, f"engines_{case}_single")
+    order_bound(rel(xm_k, ref.x), spread, f"engines_{case}_multi")
+    # converged (relres 1e-13): both engines against the oracle at the flat 1e-10
+    refc = O.plss_residual(sysm.A, sysm.b, tol=CONVERGED_TOL, maxit=200000, wi=wi)
+    assert refc.status == O.OK
+    for eng in ("single", "multi"):
+        xc, ic, _ = plss.solve(h, M, sysm.b, tol=CONVERGED_TOL, maxit=200000, wi=wi, engine=eng)
+        assert ic["status"] == 0, ic
+        converged_check(xc, refc.x, f"engines_{case}_{eng}")
     # the first iterates (before rounding differences are amplified)
     x5, _, h5 = plss.solve(h, M, sysm.b, tol=1e-300, maxit=5, wi=wi, engine="single")
     r5 = O.plss_residual(sysm.A, sysm.b, tol=1e-300, maxit=5, wi=wi)
@@ -161,7 +168,14 @@ def test_small_engine_batch(h):
         assert inf["iters"] == ia["iters"]
         np.testing.assert_array_equal(x, xa)
         ref, spread = order_spread(s.A, s.b, inf["iters"])
-        assert rel(x, ref.x) <= max(1e-10, 4 * spread)
+        order_bound(rel(x, ref.x), spread, f"small_engine_batch_{s.A.m}x{s.A.n}")
+    # converged batch (relres 1e-13) against the oracle at the flat 1e-10
+    xs, infos = plss.solve_batch(h, mats, [s.b for s in systems], tol=CONVERGED_TOL, maxit=50000)
+    for s, x, inf in zip(systems, xs, infos):
+        assert inf["status"] == 0, inf
+        ref = O.plss_residual(s.A, s.b, tol=CONVERGED_TOL, maxit=50000)
+        assert ref.status == O.OK
+        converged_check(x, ref.x, f"small_engine_batch_{s.A.m}x{s.A.n}")
 
 
 def test_small_engine_deterministic(h):

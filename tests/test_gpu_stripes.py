@@ -14,7 +14,7 @@ import pytest
 import plss_inputs as gen
 from oracle import plss as O
 
-from gpu_common import fp64_parity, matrix, order_spread, rel
+from gpu_common import CONVERGED_TOL, converged_check, fp64_parity, matrix, order_bound, order_spread, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -121,7 +121,8 @@ def test_stripe_solve_matches_oracle(h, R):
     """Zipf rows, 60000 x 15000: striped products in both directions."""
     say("stripe solve zipf", R)
     sysm = gen.large(m=60000, n=15000)
-    x, info, M = fp64_parity(h, sysm, layout={"a_stripes": True, "t_stripes": True, "unit_rows": R})
+    x, info, M = fp64_parity(h, sysm, layout={"a_stripes": True, "t_stripes": True, "unit_rows": R},
+                             case=f"zipf_60000x15000_stripes_R{R}")
     assert info["relres_true"] <= 1.5e-8
 
 
@@ -132,7 +133,8 @@ def test_stripe_solve_weighted_W(h):
     sysm = gen.large(m=60000, n=15000)
     S = sysm.A.scipy()
     wi = np.sqrt(np.asarray(S.multiply(S).sum(axis=0)).ravel())
-    x, info, M = fp64_parity(h, sysm, wi=wi, layout={"a_stripes": True, "t_stripes": True})
+    x, info, M = fp64_parity(h, sysm, wi=wi, layout={"a_stripes": True, "t_stripes": True},
+                             case="zipf_60000x15000_stripes_W")
     assert info["relres_true"] <= 1.5e-8
 
 
@@ -160,7 +162,12 @@ def test_stripe_solve_ragged_matches_oracle(h):
     x, info, _ = plss.solve(h, M, b, tol=1e-8, maxit=20000)
     assert info["status"] == 0, info
     ref, spread = order_spread(A, b, info["iters"])
-    assert rel(x, ref.x) <= max(1e-10, 4 * spread)
+    order_bound(rel(x, ref.x), spread, "ragged_3000x9000_stripes")
+    x, info, _ = plss.solve(h, M, b, tol=CONVERGED_TOL, maxit=50000)
+    assert info["status"] == 0, info
+    ref = O.plss_residual(A, b, tol=CONVERGED_TOL, maxit=50000)
+    assert ref.status == O.OK
+    converged_check(x, ref.x, "ragged_3000x9000_stripes")
 
 
 def test_stripe_equals_tiles_first_iterates(h):
