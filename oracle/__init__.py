@@ -11,7 +11,10 @@ Contents (plain, slow, obviously correct; float64 unless stated):
 * ``plss``    Algorithm 1 (residual sketch, optional diagonal W) and the
               general one-column sketch step (identity / mixed / residual
               sketches, Sections 2.5-2.6 and 7).
-* ``exact``   The same two iterations in rational arithmetic
+* ``blocks``  PLSS with a sketch grown by a block of columns per step (block
+              identity, or residual plus identity columns), by the block form
+              of the triangular update of Section 2.4.
+* ``exact``   The same iterations in rational arithmetic
               (``fractions.Fraction``) on small integer systems, plus a
               rational minimum-norm solve.
 * ``pins``    Independent routines the oracle is checked against: a dense

@@ -158,3 +158,77 @@ def min_norm_exact(A, b) -> Vec:
     AtA = [[sum((A[i][a] * A[i][c] for i in range(m)), Fraction(0)) for c in range(n)]
            for a in range(n)]
     return solve_exact(AtA, mtv(A, b))
+
+
+def plss_blocks_exact(A, b, blocks, used=None):
+    """Block sketch steps in rationals (the block form of the triangular
+    update of Section 2.4, as ``oracle.blocks``).  ``blocks`` is a list of
+    lists of columns ('r',) / ('e', i), or ('clear',) to empty the history.
+    In block order, a column whose Schur-complement pivot is exactly zero
+    (y_j in the span of the history and the block's earlier kept columns) is
+    left out; a step with no kept column is not an update.  Returns (x,
+    residuals, updates); the kept columns of each update go to ``used``."""
+    A = mat(A); b = vec(b)
+    m, n = len(A), len(A[0])
+    x = [Fraction(0)] * n
+    r = list(b)
+    Y: List[Vec] = []          # history columns y_j (each length n)
+    N: Mat = []                # (Yᵀ Y)^{-1}
+    rs, ps = [list(r)], []
+    for blk in blocks:
+        if blk == ("clear",):
+            Y, N = [], []
+            continue
+        if dot(r, r) == 0:
+            break
+        ynew, sig = [], []
+        for col in blk:
+            if col[0] == "r":
+                ynew.append(mtv(A, r)); sig.append(dot(r, r))
+            else:
+                ynew.append(list(A[col[1]])); sig.append(r[col[1]])
+        w, K = len(blk), len(Y)
+        G = [[dot(Y[a], ynew[j]) for j in range(w)] for a in range(K)]          # Yᵀ Y_new
+        T = [[sum((N[a][c] * G[c][j] for c in range(K)), Fraction(0)) for j in range(w)] for a in range(K)]
+        D = [[dot(ynew[a], ynew[j]) - sum((G[c][a] * T[c][j] for c in range(K)), Fraction(0))
+              for j in range(w)] for a in range(w)]
+        keep = []
+        for j in range(w):
+            if keep:
+                Dk = [[D[a][c] for c in keep] for a in keep]
+                z = solve_exact(Dk, [D[a][j] for a in keep])
+                piv = D[j][j] - sum((D[j][a] * za for a, za in zip(keep, z)), Fraction(0))
+            else:
+                piv = D[j][j]
+            if piv != 0:
+                keep.append(j)
+        if not keep:
+            continue
+        kw = len(keep)
+        Dk = [[D[a][c] for c in keep] for a in keep]
+        # Delta^{-1} column by column
+        Dinv_cols = [solve_exact(Dk, [Fraction(int(i == j)) for i in range(kw)]) for j in range(kw)]
+        Dinv = [[Dinv_cols[c][a] for c in range(kw)] for a in range(kw)]
+        c = [sum((Dinv[a][q] * sig[keep[q]] for q in range(kw)), Fraction(0)) for a in range(kw)]
+        Tk = [[T[a][j] for j in keep] for a in range(K)]
+        # q_j = y_j - Y T_hat_j, p = Σ_j c_j q_j
+        p = [Fraction(0)] * n
+        for q_i, j in enumerate(keep):
+            qv = list(ynew[j])
+            for a in range(K):
+                qv = axpy(-Tk[a][q_i], Y[a], qv)
+            p = axpy(c[q_i], qv, p)
+        r = axpy(Fraction(-1), mv(A, p), r)
+        x = axpy(Fraction(1), p, x)
+        # N_k = [[N + T D^-1 Tᵀ, -T D^-1], [-D^-1 Tᵀ, D^-1]]
+        TD = [[sum((Tk[a][q] * Dinv[q][j] for q in range(kw)), Fraction(0)) for j in range(kw)] for a in range(K)]
+        newN = [[N[a][c2] + sum((TD[a][q] * Tk[c2][q] for q in range(kw)), Fraction(0)) for c2 in range(K)]
+                + [-TD[a][j] for j in range(kw)] for a in range(K)]
+        for q in range(kw):
+            newN.append([-TD[c2][q] for c2 in range(K)] + [Dinv[q][j] for j in range(kw)])
+        N = newN
+        Y = Y + [ynew[j] for j in keep]
+        rs.append(r); ps.append(p)
+        if used is not None:
+            used.append([tuple(blk[j]) for j in keep])
+    return x, rs, ps
