@@ -14,6 +14,10 @@ Contents (plain, slow, obviously correct; float64 unless stated):
 * ``blocks``  PLSS with a sketch grown by a block of columns per step (block
               identity, or residual plus identity columns), by the block form
               of the triangular update of Section 2.4.
+* ``randproj`` The paper's randomized-projection comparison (eq. pkLong with
+              a fresh standard normal sketch each iteration), with
+              Philox4x32-10 and Box-Muller written from their published
+              definitions so the GPU can draw the same sketches.
 * ``exact``   The same iterations in rational arithmetic
               (``fractions.Fraction``) on small integer systems, plus a
               rational minimum-norm solve.
