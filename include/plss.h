@@ -185,6 +185,29 @@ plss_status plss_matrix_layout(plss_handle* h, plss_matrix* A, const plss_layout
 plss_status plss_spmv(plss_handle* h, const plss_matrix* A, int transpose, const double* x,
                       double* y);
 
+/* Bytes of the fixed device array behind plss_spmv_noalloc: one per GPU the
+ * library runs on, held from the library's load until the process ends. */
+#define PLSS_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * product as plss_spmv, computed by the same kernels (bit-identical results),
+ * with no hipMalloc, hipFree or host-pinned allocation.  x (length n, or m
+ * for transpose = 1) and y (length m, or n) must be device memory of the
+ * handle's GPU and must not overlap; the caller owns both.  The scratch of
+ * the product (launch descriptor, launch list and, for the striped
+ * transposed product, the per-row-block partial vectors: 8 * row blocks * n
+ * bytes) lives in that GPU's fixed array of PLSS_NOALLOC_SCRATCH_BYTES; its
+ * device address is looked up once per GPU at plss_create.  The array keeps
+ * the last call's contents; nothing in it needs to start at zero.  Calls in
+ * one process that use the same GPU share the array and are serialised by a
+ * lock (overlapping calls would race on it); returns when y is complete.
+ * Errors: EINVAL for host or foreign-device pointers, overlapping x and y,
+ * or a product whose scratch exceeds the array (the message gives both
+ * sizes); EDEVICE if the array's address cannot be found. */
+plss_status plss_spmv_noalloc(plss_handle* h, const plss_matrix* A, int transpose, const double* x,
+                              double* y);
+
 /* Solve A x = b (b length m, x length n).  res_hist (may be NULL) receives
  * up to hist_cap entries sqrt(rho_k)/||b||, k = 0..iters (the recursive
  * residual of Algorithm 1).  Returns the system's status (OK, NOT_CONVERGED,

@@ -272,6 +272,23 @@ def spmv(handle: Handle, A: Matrix, x, transpose=False):
     return y
 
 
+def spmv_noalloc(handle: Handle, A: Matrix, x, y, transpose=False):
+    """y <- A x (or Aᵀ x) through plss_spmv_noalloc: x and y are float64
+    device tensors of the handle's GPU, y preallocated by the caller; the
+    library allocates nothing.  Returns y."""
+    if not (_is_torch(x) and _is_torch(y) and x.is_cuda and y.is_cuda):
+        raise TypeError("spmv_noalloc takes device tensors (x, y)")
+    import torch
+    if x.dtype != torch.float64 or y.dtype != torch.float64 or not x.is_contiguous() or not y.is_contiguous():
+        raise TypeError("x and y must be contiguous float64 tensors")
+    nin, nout = (A.m, A.n) if transpose else (A.n, A.m)
+    if x.numel() != nin or y.numel() != nout:
+        raise ValueError(f"x must hold {nin} and y {nout} entries")
+    torch.cuda.current_stream(x.device).synchronize()
+    _check(_clib().plss_spmv_noalloc(handle.h, A.A, int(bool(transpose)), x.data_ptr(), y.data_ptr()))
+    return y
+
+
 def kernel_times(handle: Handle):
     """Accumulated per-kernel device ms and launch counts since the last call:
     [product with A, product with Aᵀ, step scalars, vector update]."""

@@ -26,6 +26,7 @@ SOURCES = [
     "multi_kernels.hip",
     "stripe.hip",
     "small.hip",
+    "noalloc.hip",
     "runtime.cpp",
     "solve.cpp",
     "ops.cpp",

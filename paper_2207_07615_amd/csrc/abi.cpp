@@ -87,6 +87,7 @@ plss_status plss_create(plss_handle** out, int device) {
   PLSS_HIP(hipGetDeviceCount(&count));
   if (device < 0 || device >= count) throw InvalidArg{"no such device"};
   DeviceScope ds(device);
+  (void)scratch_ptr(device);  // this GPU's copy of the fixed scratch array (once per device)
   plss_handle* h = new plss_handle();
   h->device = device;
   hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
@@ -212,6 +213,17 @@ plss_status plss_spmv(plss_handle* h, const plss_matrix* A, int transpose, const
   DeviceScope ds(h->device);
   std::lock_guard<std::mutex> lk(h->mu);
   spmv_plain(A, transpose != 0, x, y, h->stream);
+  return PLSS_OK;
+  PLSS_GUARD_END
+}
+
+plss_status plss_spmv_noalloc(plss_handle* h, const plss_matrix* A, int transpose, const double* x,
+                              double* y) {
+  PLSS_GUARD_BEGIN
+  if (!h || !A || !x || !y) throw InvalidArg{"null argument"};
+  DeviceScope ds(h->device);
+  std::lock_guard<std::mutex> lk(h->mu);
+  spmv_noalloc(h, A, transpose != 0, x, y, h->stream);
   return PLSS_OK;
   PLSS_GUARD_END
 }
