@@ -647,41 +647,140 @@ __global__ __launch_bounds__(kWG) void k_csc_scatter(const int* __restrict__ ptr
   }
 }
 
-// sort each column segment by row (rows are distinct inside a column, so the
-// rank of an entry is the number of smaller rows): one wave per column
+// sort each column segment of at most kCscShort entries by row (rows are
+// distinct inside a column, so the rank of an entry is the number of smaller
+// rows): one wave per column, keys in LDS.  Longer columns are listed for
+// k_csc_sort_long.
+constexpr int kCscShort = 512;
 __global__ __launch_bounds__(kWG) void k_csc_sort(const int* __restrict__ cptr, int n,
                                                   const int* __restrict__ row_in,
                                                   const int* __restrict__ pos_in,
                                                   int* __restrict__ row_out,
-                                                  int* __restrict__ pos_out) {
-  constexpr int kCap = 512;
-  __shared__ int s_key[kWaves][kCap];
+                                                  int* __restrict__ pos_out,
+                                                  int* __restrict__ long_cols,
+                                                  int* __restrict__ n_long) {
+  __shared__ int s_key[kWaves][kCscShort];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wave = (blockIdx.x * kWG + threadIdx.x) >> 6;
   const int nwaves = (gridDim.x * kWG) >> 6;
   for (int j = wave; j < n; j += nwaves) {
     const int b = cptr[j], len = cptr[j + 1] - b;
-    if (len <= kCap) {
-      for (int q = lane; q < len; q += 64) s_key[w][q] = row_in[b + q];
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-      for (int q = lane; q < len; q += 64) {
-        const int key = s_key[w][q];
-        int rank = 0;
-        for (int o = 0; o < len; ++o) rank += s_key[w][o] < key;
-        row_out[b + rank] = key;
-        pos_out[b + rank] = pos_in[b + q];
+    if (len > kCscShort) {
+      if (lane == 0) long_cols[atomicAdd(n_long, 1)] = j;
+      continue;
+    }
+    for (int q = lane; q < len; q += 64) s_key[w][q] = row_in[b + q];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    for (int q = lane; q < len; q += 64) {
+      const int key = s_key[w][q];
+      int rank = 0;
+      for (int o = 0; o < len; ++o) rank += s_key[w][o] < key;
+      row_out[b + rank] = key;
+      pos_out[b + rank] = pos_in[b + q];
+    }
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  }
+}
+
+// Columns longer than kCscShort: one workgroup per column, a least-
+// significant-digit radix sort of the (row, position) pairs by row with
+// 4-bit digits, linear in the column length per pass.  Each pass counts the
+// column's digits, then walks the column in tiles of 4096 in order: a thread
+// takes 4 consecutive entries, the (digit, thread) counts are scanned in
+// digit-major order, and every entry goes to its digit's next free slot in
+// entry order (stable).  Passes alternate between the two buffer pairs; an
+// odd pass count ends in (row_b, pos_b).
+constexpr int kSortT = 1024;
+__global__ __launch_bounds__(kSortT) void k_csc_sort_long(const int* __restrict__ cptr,
+                                                          const int* __restrict__ long_cols,
+                                                          const int* __restrict__ n_long, int passes,
+                                                          int* row_a, int* pos_a, int* row_b, int* pos_b) {
+  __shared__ int s_cnt[16 * kSortT];
+  __shared__ int s_sum[kSortT];
+  __shared__ int s_base[16], s_tot[16], s_dstart[17];
+  const int t = threadIdx.x;
+  const int nl = *n_long;
+  for (int ci = blockIdx.x; ci < nl; ci += gridDim.x) {
+    const int j = long_cols[ci];
+    const int b = cptr[j], len = cptr[j + 1] - b;
+    int* rin = row_a + b;
+    int* pin = pos_a + b;
+    int* rout = row_b + b;
+    int* pout = pos_b + b;
+    for (int pass = 0; pass < passes; ++pass) {
+      const int sh = 4 * pass;
+      if (t < 16) s_tot[t] = 0;
+      __syncthreads();
+      for (int e = t; e < len; e += kSortT) atomicAdd(&s_tot[sh < 32 ? ((rin[e] >> sh) & 15) : 0], 1);
+      __syncthreads();
+      if (t == 0) {
+        int acc = 0;
+        for (int d = 0; d < 16; ++d) {
+          s_base[d] = acc;
+          acc += s_tot[d];
+        }
       }
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    } else {
-      for (int q = lane; q < len; q += 64) {
-        const int key = row_in[b + q];
-        int rank = 0;
-        for (int o = 0; o < len; ++o) rank += row_in[b + o] < key;
-        row_out[b + rank] = key;
-        pos_out[b + rank] = pos_in[b + q];
+      __syncthreads();
+      for (int t0 = 0; t0 < len; t0 += 4 * kSortT) {
+        int key[4], pos[4], dig[4];
+        int c[16];
+#pragma unroll
+        for (int d = 0; d < 16; ++d) c[d] = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = t0 + 4 * t + u;
+          key[u] = e < len ? rin[e] : 0;
+          pos[u] = e < len ? pin[e] : 0;
+          dig[u] = e < len ? (sh < 32 ? ((key[u] >> sh) & 15) : 0) : -1;
+#pragma unroll
+          for (int d = 0; d < 16; ++d) c[d] += dig[u] == d;
+        }
+#pragma unroll
+        for (int d = 0; d < 16; ++d) s_cnt[d * kSortT + t] = c[d];
+        __syncthreads();
+        // exclusive scan of s_cnt in digit-major order: thread t owns
+        // entries [16 t, 16 t + 16)
+        int loc[16];
+        int run = 0;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          loc[q] = run;
+          run += s_cnt[16 * t + q];
+        }
+        s_sum[t] = run;
+        __syncthreads();
+        for (int off = 1; off < kSortT; off <<= 1) {
+          const int v = t >= off ? s_sum[t - off] : 0;
+          __syncthreads();
+          s_sum[t] += v;
+          __syncthreads();
+        }
+        const int pre = s_sum[t] - run;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) s_cnt[16 * t + q] = pre + loc[q];
+        __syncthreads();
+        if (t <= 16) s_dstart[t] = t < 16 ? s_cnt[t * kSortT] : s_sum[kSortT - 1];
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int d = dig[u];
+          if (d < 0) continue;
+          int before = 0;
+#pragma unroll
+          for (int v = 0; v < u; ++v) before += dig[v] == d;
+          const int slot = s_base[d] + (s_cnt[d * kSortT + t] - s_dstart[d]) + before;
+          rout[slot] = key[u];
+          pout[slot] = pos[u];
+        }
+        __syncthreads();
+        if (t < 16) s_base[t] += s_dstart[t + 1] - s_dstart[t];
+        __syncthreads();
       }
+      int* tr = rin; rin = rout; rout = tr;
+      int* tp = pin; pin = pout; pout = tp;
+      __syncthreads();
     }
   }
 }
@@ -775,7 +874,8 @@ void launch_update(bool f32, const Desc* d, const int2* ulist, int n, hipStream_
 
 void build_csc(const int* ptr, const int* idx, const double* vals64, int m, int n, long long nnz,
                bool f32, int* cptr, int* ridx, void* cvals, void* work, hipStream_t s) {
-  // work layout: cnt[n] | cursor[n+1] | bsum[nb+1] (int64) | row_tmp[nnz] | pos_tmp[nnz] | pos[nnz]
+  // work layout: cnt[n] | cursor[n+1] | bsum[nb+1] (int64) | row_tmp[nnz] | pos_tmp[nnz] | pos[nnz] |
+  // long_cols[n] | n_long
   char* w = static_cast<char*>(work);
   int* cnt = reinterpret_cast<int*>(w);
   w += sizeof(int) * ((size_t)n + 64);
@@ -789,6 +889,10 @@ void build_csc(const int* ptr, const int* idx, const double* vals64, int m, int 
   int* pos_tmp = reinterpret_cast<int*>(w);
   w += sizeof(int) * ((size_t)nnz + 64);
   int* pos = reinterpret_cast<int*>(w);
+  w += sizeof(int) * ((size_t)nnz + 64);
+  int* long_cols = reinterpret_cast<int*>(w);
+  w += sizeof(int) * ((size_t)n + 64);
+  int* n_long = reinterpret_cast<int*>(w);
 
   PLSS_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * (size_t)n, s));
   if (nnz > 0) k_csc_count<<<grid_for(nnz), kWG, 0, s>>>(idx, nnz, cnt);
@@ -798,7 +902,15 @@ void build_csc(const int* ptr, const int* idx, const double* vals64, int m, int 
   PLSS_HIP(hipMemcpyAsync(cursor, cptr, sizeof(int) * (size_t)n, hipMemcpyDeviceToDevice, s));
   if (nnz > 0) {
     k_csc_scatter<<<grid_for((long long)m * 64, kWG), kWG, 0, s>>>(ptr, idx, m, cursor, row_tmp, pos_tmp);
-    k_csc_sort<<<grid_for((long long)n * 64, kWG), kWG, 0, s>>>(cptr, n, row_tmp, pos_tmp, ridx, pos);
+    PLSS_HIP(hipMemsetAsync(n_long, 0, sizeof(int), s));
+    k_csc_sort<<<grid_for((long long)n * 64, kWG), kWG, 0, s>>>(cptr, n, row_tmp, pos_tmp, ridx, pos, long_cols,
+                                                                n_long);
+    // digit passes over the row indices (an odd count ends in ridx / pos)
+    int bits = 1;
+    while (bits < 31 && (1LL << bits) < (long long)m) ++bits;
+    int passes = (bits + 3) / 4;
+    if (passes % 2 == 0) ++passes;
+    k_csc_sort_long<<<256, kSortT, 0, s>>>(cptr, long_cols, n_long, passes, row_tmp, pos_tmp, ridx, pos);
     if (f32) k_gather_vals<float><<<grid_for(nnz), kWG, 0, s>>>(pos, nnz, vals64, static_cast<float*>(cvals));
     else k_gather_vals<double><<<grid_for(nnz), kWG, 0, s>>>(pos, nnz, vals64, static_cast<double*>(cvals));
   }
@@ -807,8 +919,8 @@ void build_csc(const int* ptr, const int* idx, const double* vals64, int m, int 
 
 size_t csc_work_bytes(int n, long long nnz) {
   const int nb = (n + 1023) / 1024;
-  return sizeof(int) * ((size_t)n + 64) * 2 + sizeof(long long) * ((size_t)nb + 64) +
-         sizeof(int) * ((size_t)nnz + 64) * 3;
+  return sizeof(int) * ((size_t)n + 64) * 3 + sizeof(long long) * ((size_t)nb + 64) +
+         sizeof(int) * ((size_t)nnz + 64) * 3 + 256;
 }
 
 void convert_vals(const double* src, long long nnz, bool f32, void* dst, hipStream_t s) {

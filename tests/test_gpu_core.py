@@ -41,11 +41,36 @@ def ragged_matrix(seed, m, n):
     return gen.make_csr(rng, m, n, L, "normal")
 
 
-@pytest.mark.parametrize("case", ["small", "ragged", "wide", "single"])
+def long_columns_matrix(seed=6, m=100_000, n=3000):
+    """Column 0 in every row (10^5 entries), column 1 in 513 rows, column 2
+    in 4097 rows and column 3 in 12,293 rows (columns longer than a wave's
+    in-LDS sort, in one or several 4096-entry tiles of the long-column
+    sort), plus 3 random columns per row."""
+    import scipy.sparse as sp
+    rng = gen.rng_for(seed)
+    rows, cols = [], []
+    for c, cnt in ((0, m), (1, 513), (2, 4097), (3, 12293)):
+        rr = np.sort(rng.choice(m, cnt, replace=False))
+        rows.append(rr)
+        cols.append(np.full(cnt, c))
+    rr = np.repeat(np.arange(m), 3)
+    rows.append(rr)
+    cols.append(rng.integers(4, n, size=rr.size))
+    rows = np.concatenate(rows)
+    cols = np.concatenate(cols)
+    S = sp.csr_matrix((rng.standard_normal(rows.size), (rows, cols)), shape=(m, n))
+    S.sum_duplicates()
+    S.sort_indices()
+    return gen.CSR(m, n, S.indptr.astype(np.int64), S.indices.astype(np.int32), S.data.astype(np.float64))
+
+
+@pytest.mark.parametrize("case", ["small", "ragged", "wide", "single", "long_columns"])
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_csc_bit_exact(h, case, storage):
     say("csc", case, storage)
-    if case == "small":
+    if case == "long_columns":
+        A = long_columns_matrix()
+    elif case == "small":
         A = gen.small(m=3000, n=1500).A
     elif case == "ragged":
         A = ragged_matrix(3, 9000, 6000)
