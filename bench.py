@@ -196,8 +196,33 @@ def run_small(args):
                                    "sample": f"{nref} full solves of {ref.iters} iterations ({tc:.1f} s)"})
 
 
+def column_bytes(m, n, nnz, kh, residual):
+    """Algorithmic bytes of one one-column sketch step with kh stored
+    updates (float64, int32 indices): a residual column adds y = Aᵀ r
+    (12 nnz + 4n + 8n + 8m) and (AP)ᵀ r (8 m kh + 8m); every column reads P
+    for p = gamma (y - P c) (8 n kh + 8n, writes p and updates x: 24n) and
+    runs A p into AP and r (12 nnz + 4m + 8n + 8m + 16m)."""
+    b = 8 * n * kh + 8 * n + 24 * n + 12 * nnz + 4 * m + 8 * n + 24 * m
+    if residual:
+        b += 12 * nnz + 12 * n + 8 * m + 8 * m * kh + 8 * m
+    return b
+
+
+def block_bytes(m, n, nnz, K, w, residual):
+    """Algorithmic bytes of one block step with K stored history columns and
+    w columns in the block: [y = Aᵀ r and (A Z)ᵀ r: 12 nnz + 12n + 8m +
+    8 m K + 8m]; Z_new = Y_new - Z C reads Z and y, writes Z_new, updates x
+    (8 n K + 8n + 8 n w + 16n); A Z_new into the history and r (12 nnz + 4m +
+    8 n w + 8 m w + 16m)."""
+    b = 8 * n * K + 8 * n + 8 * n * w + 16 * n + 12 * nnz + 4 * m + 8 * n * w + 8 * m * w + 16 * m
+    if residual:
+        b += 12 * nnz + 12 * n + 8 * m + 8 * m * K + 8 * m
+    return b
+
+
 def run_underdet(args):
-    """200,000 x 1,000,000, 30 nnz per row, U(-1,1), mixed sketch, FP64."""
+    """200,000 x 1,000,000, 30 nnz per row, U(-1,1), mixed sketch, FP64; and
+    the same system with mixed blocks of 15 rows (16 columns per step)."""
     import numpy as np
     import paper_2207_07615_amd as plss
     import plss_inputs as gen
@@ -209,25 +234,52 @@ def run_underdet(args):
     kw = dict(sketch="mixed", tol=1e-8, maxit=2000, row_perm=sysm.perm, hist_cap=128)
     for _ in range(args.warmup):
         plss.solve(h, M, sysm.b, **kw)
-    its, dev = [], []
+    its, dev, cols = [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         x, info, _ = plss.solve(h, M, sysm.b, **kw)
         its.append(info["iters"])
         dev.append(info["ms"])
+        cols.append(info["outer_iters"])
     wall = time.perf_counter() - t0
+    # bytes of the columns of one solve: columns alternate residual / identity,
+    # the history holds the updates so far (no skip, no clear at this size)
+    nupd = its[-1]
+    col_b = sum(column_bytes(A.m, A.n, A.nnz, t // 2, t % 2 == 0) for t in range(cols[-1]))
+    # mixed blocks of 15 identity rows plus r (one MFMA tile of 16 columns)
+    kwb = dict(sketch="block_mixed", block=15, tol=1e-8, maxit=2000, row_perm=sysm.perm, hist_cap=256)
+    for _ in range(args.warmup):
+        plss.solve(h, M, sysm.b, **kwb)
+    itb, devb = [], []
     t1 = time.perf_counter()
+    for _ in range(args.steps):
+        xb, ib, _ = plss.solve(h, M, sysm.b, **kwb)
+        itb.append(ib["iters"])
+        devb.append(ib["ms"])
+    wallb = time.perf_counter() - t1
+    blk_b = sum(block_bytes(A.m, A.n, A.nnz, 16 * (t % 16), 16, True) for t in range(itb[-1]))
+    t2 = time.perf_counter()
     ref = O.plss_columns(A, sysm.b, "mixed", perm=sysm.perm, tol=1e-300, maxit=8, hist_cap=128)
-    tc = time.perf_counter() - t1
+    tc = time.perf_counter() - t2
     x8, i8, _ = plss.solve(h, M, sysm.b, sketch="mixed", tol=1e-300, maxit=8, row_perm=sysm.perm, hist_cap=128)
     return base_line(METRIC, sum(its) / wall, "updates/s", args.steps, args.warmup, wall, "f64",
                      {"workload": "underdet: 200,000 x 1,000,000 CSR, 30 nnz/row, U(-1,1), mixed sketch "
                                   "(residual + identity columns), FP64, tol 1e-8",
                       "m": A.m, "n": A.n, "nnz": A.nnz, "hist_cap": 128},
                      solves_per_s=args.steps / wall, updates_per_solve=sum(its) / len(its),
+                     columns_per_solve=sum(cols) / len(cols),
                      device_ms_per_solve=sum(dev) / len(dev),
                      relres_true=info["relres_true"], status=info["status_name"],
+                     roofline=aggregate_roofline(col_b * args.steps, wall, "whole solves (all column steps)"),
                      rel_err_vs_oracle_8_updates=float(np.linalg.norm(x8 - ref.x) / np.linalg.norm(ref.x)),
+                     mixed_blocks_15={"solves_per_s": args.steps / wallb, "ms_per_solve": 1e3 * wallb / args.steps,
+                                      "block_steps_per_solve": sum(itb) / len(itb),
+                                      "device_ms_per_solve": sum(devb) / len(devb),
+                                      "relres_true": ib["relres_true"], "status": ib["status_name"],
+                                      "hist_cap": 256,
+                                      "roofline": aggregate_roofline(blk_b * args.steps, wallb,
+                                                                     "whole solves (all block steps)"),
+                                      "solves_per_s_vs_one_column": (args.steps / wallb) / (args.steps / wall)},
                      cpu_baseline={"value": ref.iters / tc, "unit": "updates/s", "cores": 1, "kind": "oracle",
                                    "sample": f"first {ref.iters} column steps ({tc:.1f} s)"})
 
@@ -475,6 +527,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 + refinement arm")
     ap.add_argument("--no-w", action="store_true", help="skip the PLSS W arm (column-norm weights)")
+    ap.add_argument("--no-rp", action="store_true", help="skip the randomized-projection arm")
     ap.add_argument("--autotune", action="store_true", help="pick tile widths by measurement")
     ap.add_argument("--layout", default="auto", choices=["auto", "tiles", "stripes"],
                     help="product layout of the large workload (auto: chosen from the shape)")
@@ -652,6 +705,24 @@ def main():
             "iters_per_solve": sum(itsw) / nw, "iters_per_s": sum(itsw) / ww,
             "relres_true": iw["relres_true"], "status": iw["status_name"],
             "solves_per_s_vs_plain": (nw / ww) / (args.steps / wall),
+        }
+
+    if not args.no_rp:
+        # the paper's randomized projection (fresh 5-column Gaussian sketch per
+        # iteration, r = 5 for n > 1e5 as in Experiment III) for a fixed number
+        # of iterations, against Algorithm 1 after as many iterations
+        krp = 100
+        kwr = dict(sketch="randproj", block=5, seed=761512, tol=1e-300, maxit=krp)
+        plss.solve(h, M, b, **dict(kwr, maxit=2))
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        xr, ir, _ = plss.solve(h, M, b, **kwr)
+        torch.cuda.synchronize()
+        wr = time.perf_counter() - t1
+        xp, ip, _ = plss.solve(h, M, b, tol=1e-300, maxit=krp)
+        out["randproj_r5"] = {
+            "iters": ir["iters"], "iters_per_s": ir["iters"] / wr, "ms_per_iter": 1e3 * wr / ir["iters"],
+            "relres_true_after": ir["relres_true"], "plss_relres_true_after_same_iters": ip["relres_true"],
         }
 
     if not args.no_cpu:

@@ -51,7 +51,12 @@ typedef enum {
 typedef enum {
   PLSS_SKETCH_RESIDUAL = 0, /* eq. S, Algorithm 1 */
   PLSS_SKETCH_IDENTITY = 1, /* Section 7 (PLSS KZ) */
-  PLSS_SKETCH_MIXED = 2     /* r_{k-1}, e_{i}, r, e, ... alternating */
+  PLSS_SKETCH_MIXED = 2,    /* r_{k-1}, e_{i}, r, e, ... alternating */
+  PLSS_SKETCH_BLOCK_IDENTITY = 3, /* opts.block identity columns appended per step: the
+                                     block form of the triangular update of Section 2.4 */
+  PLSS_SKETCH_BLOCK_MIXED = 4,    /* r_{k-1} and opts.block identity columns per step */
+  PLSS_SKETCH_RANDPROJ = 5        /* Section 8's randomized projection: eq. pkLong with a
+                                     fresh m x opts.block standard normal sketch per step */
 } plss_sketch;
 
 typedef enum {
@@ -86,8 +91,9 @@ typedef struct {
                            (Section 4.1); NULL means W = I.  Residual sketch only. */
   const int32_t* row_perm; /* identity/mixed: order of identity columns, a permutation
                               of 0..m-1 reused cyclically; NULL means 0..m-1 */
-  int64_t hist_cap;     /* identity/mixed: history columns kept before the stored
-                           P, AP are cleared (0: min(m, n, 256)) */
+  int64_t hist_cap;     /* identity/mixed/block: history columns kept before the
+                           stored history is cleared (0: min(m, n, 256); at most
+                           256 for identity/mixed, 1024 for the block sketches) */
   int32_t chunk;        /* iterations per launch batch between host checks (0: auto) */
   int32_t timing;       /* record per-kernel device times (see plss_kernel_times) */
   int32_t engine;       /* residual sketch: 0 = automatic, 1 = one launch per phase
@@ -97,6 +103,12 @@ typedef struct {
                            4 (m + n) <= 156 KiB, about m + 3.5 n <= 19,900 in
                            float64; automatic for those systems with at most 2^18
                            entries) */
+  int32_t block;        /* block sketches: identity rows per step (1..16 identity,
+                           1..15 mixed); randomized projection: sketch columns
+                           (1..16) */
+  uint64_t seed;        /* randomized projection: Philox4x32-10 key (low word, high
+                           word); entry [i, 4q + t] of the k-th sketch is normal t
+                           (Box-Muller) of the counter (i, k, q, 0) */
 } plss_opts;
 
 typedef struct {

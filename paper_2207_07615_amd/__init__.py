@@ -180,7 +180,7 @@ class Matrix:
 
 def make_opts(sketch="residual", tol=1e-8, maxit=1000, tol_absolute=False, refine=True,
               inner_tol=1e-4, max_outer=20, x0=None, wi=None, row_perm=None, hist_cap=0,
-              chunk=0, timing=False, engine="auto", keep=None):
+              chunk=0, timing=False, engine="auto", block=0, seed=0, keep=None):
     o = L.plss_opts()
     _clib().plss_opts_default(C.byref(o))
     o.sketch = L.SKETCH[sketch]
@@ -201,6 +201,8 @@ def make_opts(sketch="residual", tol=1e-8, maxit=1000, tol_absolute=False, refin
     o.chunk = int(chunk)
     o.timing = int(bool(timing))
     o.engine = L.ENGINE[engine]
+    o.block = int(block)
+    o.seed = int(seed)
     return o, keep
 
 

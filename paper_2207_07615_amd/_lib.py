@@ -11,7 +11,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libplss.so"
 
 PLSS_OK, PLSS_NOT_CONVERGED, PLSS_BREAKDOWN, PLSS_PENDING = 0, 1, 2, 3
 PLSS_EINVAL, PLSS_ENOMEM, PLSS_EDEVICE, PLSS_ECANCELLED = -1, -2, -3, -4
-SKETCH = {"residual": 0, "identity": 1, "mixed": 2}
+SKETCH = {"residual": 0, "identity": 1, "mixed": 2, "block_identity": 3, "block_mixed": 4, "randproj": 5}
 DTYPE = {"f64": 0, "float64": 0, "f32": 1, "float32": 1}
 
 
@@ -25,7 +25,8 @@ class plss_opts(C.Structure):
                 ("tol_absolute", C.c_int32), ("refine", C.c_int32), ("inner_tol", C.c_double),
                 ("max_outer", C.c_int64), ("x0", C.c_void_p), ("wi_diag", C.c_void_p),
                 ("row_perm", C.c_void_p), ("hist_cap", C.c_int64), ("chunk", C.c_int32),
-                ("timing", C.c_int32), ("engine", C.c_int32)]
+                ("timing", C.c_int32), ("engine", C.c_int32), ("block", C.c_int32),
+                ("seed", C.c_uint64)]
 
 
 class plss_info(C.Structure):

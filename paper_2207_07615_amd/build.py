@@ -27,12 +27,16 @@ SOURCES = [
     "stripe.hip",
     "small.hip",
     "noalloc.hip",
+    "block_kernels.hip",
+    "randproj_kernels.hip",
     "runtime.cpp",
     "solve.cpp",
     "ops.cpp",
     "sketch.cpp",
     "multi.cpp",
     "serve.cpp",
+    "block.cpp",
+    "randproj.cpp",
     "abi.cpp",
 ]
 

@@ -236,7 +236,11 @@ plss_status plss_solve(plss_handle* h, const plss_matrix* A, const double* b, co
   DeviceScope ds(h->device);
   std::lock_guard<std::mutex> lk(h->mu);
   plss_info inf{};
-  if (o->sketch != PLSS_SKETCH_RESIDUAL) {
+  if (o->sketch == PLSS_SKETCH_BLOCK_IDENTITY || o->sketch == PLSS_SKETCH_BLOCK_MIXED) {
+    block_solve(h, A, b, o, x, hist, hist_cap, &inf, h->stream);
+  } else if (o->sketch == PLSS_SKETCH_RANDPROJ) {
+    randproj_solve(h, A, b, o, x, hist, hist_cap, &inf, h->stream);
+  } else if (o->sketch != PLSS_SKETCH_RESIDUAL) {
     sketch_solve(h, A, b, o, x, hist, hist_cap, &inf, h->stream);
   } else {
     check_finite_inputs(A, b, o, h->stream);

@@ -20,7 +20,7 @@ void validate_opts(const plss_opts* o, bool f32) {
   if (!o) throw InvalidArg{"null opts"};
   if (!(o->tol > 0.0) || !std::isfinite(o->tol)) throw InvalidArg{"tol must be positive and finite"};
   if (o->maxit <= 0) throw InvalidArg{"maxit must be positive"};
-  if (o->sketch < PLSS_SKETCH_RESIDUAL || o->sketch > PLSS_SKETCH_MIXED)
+  if (o->sketch < PLSS_SKETCH_RESIDUAL || o->sketch > PLSS_SKETCH_RANDPROJ)
     throw InvalidArg{"unknown sketch"};
   if (f32 && o->refine && (!(o->inner_tol > 0.0) || !(o->inner_tol < 1.0)))
     throw InvalidArg{"inner_tol must be in (0, 1)"};
