@@ -130,9 +130,14 @@ void plss_opts_default(plss_opts* opts);
 
 /* Create a handle on GPU `device` (its own non-blocking stream).  The calls
  * on a handle are serialised and keep their device scratch on it between
- * calls, growing it as needed: launch tables and per-system scalars, and for
- * the identity and mixed sketches the history block of about
- * 8 (m + n) hist_cap bytes.  plss_destroy frees it. */
+ * calls, growing it as needed and never shrinking it: launch tables and
+ * per-system scalars; for the identity and mixed sketches a history block of
+ * about 8 (m + n) hist_cap bytes; for the block sketches about
+ * 8 (m + n) hist_cap bytes too (hist_cap up to 1024); for the randomized
+ * projection 8 (m + n) r bytes (r rounded up to 4).  The largest such block a
+ * handle has needed stays allocated until plss_destroy (a server created on
+ * the handle does not count it in its HBM budget; use a separate handle for
+ * sketch solves beside a server with a tight budget). */
 plss_status plss_create(plss_handle** h, int device);
 plss_status plss_destroy(plss_handle* h);
 

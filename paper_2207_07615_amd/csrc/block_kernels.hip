@@ -180,19 +180,29 @@ __global__ __launch_bounds__(kPB) void k_blk_prep(const Desc* __restrict__ d, co
     const int j = e / w, l = e % w;
     const int o = bd->bo[j], wj = bd->wh[j];
     const double* L = bd->Lh + (size_t)j * kBW * kBW;
+    // loops over the full width with the block's width as a predicate keep
+    // u in registers
     double u[kBW];
-    for (int a = 0; a < wj; ++a) {
-      double v = bd->Ug[(size_t)(o + a) * kBW + l];
+#pragma unroll
+    for (int a = 0; a < kBW; ++a) {
+      double v = a < wj ? bd->Ug[(size_t)(o + a) * kBW + l] : 0.0;
+#pragma unroll
       for (int c = 0; c < a; ++c) v -= L[a * kBW + c] * u[c];
-      u[a] = v / L[a * kBW + a];
+      u[a] = a < wj ? v / L[a * kBW + a] : 0.0;
     }
-    for (int a = 0; a < wj; ++a) bd->Ug[(size_t)(o + a) * kBW + l] = u[a];
-    for (int a = wj - 1; a >= 0; --a) {
+#pragma unroll
+    for (int a = 0; a < kBW; ++a)
+      if (a < wj) bd->Ug[(size_t)(o + a) * kBW + l] = u[a];
+#pragma unroll
+    for (int a = kBW - 1; a >= 0; --a) {
       double v = u[a];
-      for (int c = a + 1; c < wj; ++c) v -= L[c * kBW + a] * u[c];
-      u[a] = v / L[a * kBW + a];
+#pragma unroll
+      for (int c = a + 1; c < kBW; ++c) v -= L[c * kBW + a] * u[c];
+      u[a] = a < wj ? v / L[a * kBW + a] : 0.0;
     }
-    for (int a = 0; a < wj; ++a) bd->Cg[(size_t)(o + a) * kBW + l] = u[a];
+#pragma unroll
+    for (int a = 0; a < kBW; ++a)
+      if (a < wj) bd->Cg[(size_t)(o + a) * kBW + l] = u[a];
   }
   // G0 = Y_newᵀ Y_new: phi, y_rᵀ a_i, a_iᵀ a_l (upper triangle)
   for (int e = threadIdx.x; e < w * w; e += kPB) {
@@ -213,15 +223,22 @@ __global__ __launch_bounds__(kPB) void k_blk_prep(const Desc* __restrict__ d, co
     s_G[l][a] = g;
   }
   __syncthreads();
-  // Delta = G0 - Uᵀ U
-  for (int e = threadIdx.x; e < w * w; e += kPB) {
-    const int a = e / w, l = e % w;
-    if (a > l) continue;
-    double v = 0.0;
-    for (int k = 0; k < K; ++k) v += bd->Ug[(size_t)k * kBW + a] * bd->Ug[(size_t)k * kBW + l];
-    const double dd = s_G[a][l] - v;
-    s_D[a][l] = dd;
-    s_D[l][a] = dd;
+  // Delta = G0 - Uᵀ U: one wave per entry (upper triangle), its lanes over
+  // the history columns, a fixed-order wave sum
+  {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int e = wv; e < w * w; e += kPB / 64) {
+      const int a = e / w, l = e % w;
+      if (a > l) continue;
+      double v = 0.0;
+      for (int k = lane; k < K; k += 64) v += bd->Ug[(size_t)k * kBW + a] * bd->Ug[(size_t)k * kBW + l];
+      v = wsum(v);
+      if (lane == 0) {
+        const double dd = s_G[a][l] - v;
+        s_D[a][l] = dd;
+        s_D[l][a] = dd;
+      }
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -229,15 +246,19 @@ __global__ __launch_bounds__(kPB) void k_blk_prep(const Desc* __restrict__ d, co
     for (int j = 0; j < w; ++j) {
       double z[kBW];
       double zz = 0.0;
-      for (int a = 0; a < nk; ++a) {
-        double v = s_D[s_keep[a]][j];
+#pragma unroll
+      for (int a = 0; a < kBW; ++a) {
+        double v = a < nk ? s_D[s_keep[a]][j] : 0.0;
+#pragma unroll
         for (int c = 0; c < a; ++c) v -= s_L[a][c] * z[c];
-        z[a] = v / s_L[a][a];
+        z[a] = a < nk ? v / s_L[a][a] : 0.0;
         zz += z[a] * z[a];
       }
       const double piv = s_D[j][j] - zz;
       if (piv > 1e-14 * s_G[j][j]) {
-        for (int c = 0; c < nk; ++c) s_L[nk][c] = z[c];
+#pragma unroll
+        for (int c = 0; c < kBW; ++c)
+          if (c < nk) s_L[nk][c] = z[c];
         s_L[nk][nk] = sqrt(piv);
         s_keep[nk++] = j;
       } else if (j < res) {
@@ -254,15 +275,19 @@ __global__ __launch_bounds__(kPB) void k_blk_prep(const Desc* __restrict__ d, co
       bs->res_kept = (nk > 0 && res && s_keep[0] == 0) ? 1 : 0;
       // c' = (L Lᵀ)^{-1} sigma on the kept columns
       double t[kBW];
-      for (int a = 0; a < nk; ++a) {
-        double v = s_sig[s_keep[a]];
+#pragma unroll
+      for (int a = 0; a < kBW; ++a) {
+        double v = a < nk ? s_sig[s_keep[a]] : 0.0;
+#pragma unroll
         for (int c = 0; c < a; ++c) v -= s_L[a][c] * t[c];
-        t[a] = v / s_L[a][a];
+        t[a] = a < nk ? v / s_L[a][a] : 0.0;
       }
-      for (int a = nk - 1; a >= 0; --a) {
+#pragma unroll
+      for (int a = kBW - 1; a >= 0; --a) {
         double v = t[a];
-        for (int c = a + 1; c < nk; ++c) v -= s_L[c][a] * t[c];
-        t[a] = v / s_L[a][a];
+#pragma unroll
+        for (int c = a + 1; c < kBW; ++c) v -= (c < nk ? s_L[c][a] : 0.0) * t[c];
+        t[a] = a < nk ? v / s_L[a][a] : 0.0;
       }
       for (int q = 0; q < kBW; ++q) {
         bs->cp[q] = q < nk ? t[q] : 0.0;
@@ -379,7 +404,23 @@ __global__ __launch_bounds__(256) void k_blk_spmm(const Desc* __restrict__ d, co
   double acc = 0.0;
   if (i < m && q < wk) {
     const int e1 = d->a_ptr[i + 1];
-    for (int e = d->a_ptr[i]; e < e1; ++e) acc += av[e] * zn[(size_t)d->a_idx[e] * kcap + q];
+    int e = d->a_ptr[i];
+    // eight entries at a time: their indices, values and gathered rows in
+    // flight before the first product (the sum keeps the entry order)
+    for (; e + 8 <= e1; e += 8) {
+      int c[8];
+      double v[8], zv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        c[u] = d->a_idx[e + u];
+        v[u] = av[e + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) zv[u] = zn[(size_t)c[u] * kcap + q];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u] * zv[u];
+    }
+    for (; e < e1; ++e) acc += av[e] * zn[(size_t)d->a_idx[e] * kcap + q];
     bd->AZh[(size_t)i * kcap + K + q] = acc;
   }
   double rs = acc * (q < wk ? bs->cp[q] : 0.0);

@@ -49,6 +49,12 @@ constexpr int kMaxBlk = 8;         // row blocks of the transposed store (one pe
 // power of two: an entry keeps its column inside the stripe in 16 bits.
 constexpr int kSWA = 6144, kRBA = 8192;
 constexpr int kSWT = 2048, kRBT = 16384;
+// Float32 row-block stores of Aᵀ: the row sums of a 16384-row unit take
+// 64 KB, so the stripes can be 8192 wide (2 x 32 KB): four times fewer
+// stripes, and their fixed costs, than at 2048.  The plain product, which
+// accumulates in float64, runs on the CSC tiles for these stores.
+constexpr int kSWT32 = 8192;
+inline int swt(bool f32) { return f32 ? kSWT32 : kSWT; }
 constexpr int kSThreads = 1024;
 // most entries per lane in one window of a wave range (a window holds up to
 // 64 x this many entries); at the large shapes a wave's range in a stripe of
@@ -74,7 +80,7 @@ struct StripeView {
   const int* wsp;              // 16 row-aligned wave starts per segment
   int nunits, S;
   int colbase, ncols;          // columns [colbase, colbase + ncols) of the gathered vector
-  int sw;                      // stripe width (kSWA or kSWT)
+  int sw;                      // stripe width (kSWA, kSWT or kSWT32)
 };
 
 struct State {

@@ -82,7 +82,7 @@ static bool device_pointer(const void* p, int device) {
 size_t spmv_noalloc_bytes(const plss_matrix* A, bool transpose, size_t* list_count) {
   const size_t o_list = align256(sizeof(Desc));
   size_t count = 0, ypart = 0;
-  if (transpose ? A->t_striped : A->a_striped) {
+  if (transpose ? (A->t_striped && !A->f32) : A->a_striped) {
     if (!transpose) {
       count = A->SA.nunits;
     } else {
@@ -124,7 +124,7 @@ void spmv_noalloc(plss_handle* h, const plss_matrix* A, bool transpose, const do
   d.n = (int)A->n;
   d.p = const_cast<double*>(x);
   d.r64 = y;
-  const bool striped = transpose ? A->t_striped : A->a_striped;
+  const bool striped = transpose ? (A->t_striped && !A->f32) : A->a_striped;
   UnitCounts nu;
   std::memset(&nu, 0, sizeof(nu));
   if (striped) {

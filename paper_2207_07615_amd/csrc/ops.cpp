@@ -93,7 +93,9 @@ void spmv_plain(const plss_matrix* A, bool transpose, const double* x, double* y
   const size_t nin = transpose ? A->m : A->n, nout = transpose ? A->n : A->m;
   double* dx = static_cast<double*>(sc.get(8 * nin));
   double* dy = static_cast<double*>(sc.get(8 * nout));
-  if (transpose ? A->t_striped : A->a_striped) {
+  // float32 stores of Aᵀ have stripes too wide for the float64-accumulating
+  // plain product: it runs on the CSC tiles
+  if (transpose ? (A->t_striped && !A->f32) : A->a_striped) {
     PLSS_HIP(hipMemcpyAsync(dx, x, 8 * nin, hipMemcpyDefault, s));
     stripe_plain(A, transpose, dx, dy, sc, s);
     PLSS_HIP(hipMemcpyAsync(y, dy, 8 * nout, hipMemcpyDefault, s));

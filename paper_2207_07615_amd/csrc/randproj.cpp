@@ -34,7 +34,10 @@ void randproj_solve(plss_handle* h, const plss_matrix* A, const double* b, const
   char* d_lists = nullptr;
   State* h_state = nullptr;
   try {
-    run.use_stripes = false;
+    // the products with A use the striped store when the matrix has one (the
+    // partials of rho then come per unit)
+    run.use_stripes = true;
+    const bool as = A->a_striped;
     run.setup(A, b, o, std::min<long long>(o->maxit + 2, 1LL << 22), d_state, nullptr);
     run.upload(b, nullptr, nullptr, s);
     size_t off = 0;
@@ -63,19 +66,22 @@ void randproj_solve(plss_handle* h, const plss_matrix* A, const double* b, const
     State st = run.st0;
     PLSS_HIP(hipMemcpyAsync(d_desc, &d, sizeof(Desc), hipMemcpyHostToDevice, s));
     PLSS_HIP(hipMemcpyAsync(d_state, &st, sizeof(State), hipMemcpyHostToDevice, s));
+    // the A list: units of the striped store, or the CSR tile groups
+    const int na = as ? A->SA.nunits : A->A.ntiles;
     std::vector<int2> all;
-    for (int t = 0; t < A->A.ntiles; ++t) all.push_back(make_int2(0, t));
+    for (int t = 0; t < na; ++t) all.push_back(make_int2(0, t));
     d_lists = static_cast<char*>(dmalloc(sizeof(int2) * all.size() + 64));
     int2* dla = reinterpret_cast<int2*>(d_lists);
-    int* dsys = reinterpret_cast<int*>(dla + A->A.ntiles);
+    int* dsys = reinterpret_cast<int*>(dla + na);
     PLSS_HIP(hipMemcpyAsync(d_lists, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, s));
     PLSS_HIP(hipMemsetAsync(dsys, 0, sizeof(int), s));
     PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_state), sizeof(State), hipHostMallocDefault));
 
     auto outer_seq = [&]() {
-      launch_spmv(MODE_REFINE, false, A->A.V, d_desc, dla, A->A.ntiles, 0, s);
+      if (as) launch_sspmv(MODE_REFINE, false, d_desc, dla, na, 0, s);
+      else launch_spmv(MODE_REFINE, false, A->A.V, d_desc, dla, na, 0, s);
       launch_outer(d_desc, dsys, 1, s);
-      launch_start(false, d_desc, dla, A->A.ntiles, s);
+      launch_start(false, d_desc, dla, na, s);
     };
     hipEvent_t e0, e1;
     PLSS_HIP(hipEventCreate(&e0));
@@ -87,7 +93,7 @@ void randproj_solve(plss_handle* h, const plss_matrix* A, const double* b, const
       int chunk = o->chunk > 0 ? o->chunk : 16;
       while (true) {
         for (int c = 0; c < chunk; ++c)
-          launch_rp_step(d_desc, d_rd, rp, m, n, A->A.V, dla, A->A.ntiles, ngram, nsig, s);
+          launch_rp_step(d_desc, d_rd, rp, m, n, A->A.V, dla, na, as, ngram, nsig, s);
         PLSS_HIP(hipMemcpyAsync(h_state, d_state, sizeof(State), hipMemcpyDeviceToHost, s));
         PLSS_HIP(hipStreamSynchronize(s));
         if (h_state->done || h_state->final_done) break;

@@ -23,6 +23,6 @@ struct RpDesc {
 };
 
 void launch_rp_step(const Desc* d, const RpDesc* rd, int rp, int m, int n, int AV, const int2* alist, int na,
-                    int ngram, int nsig, hipStream_t s);
+                    bool striped, int ngram, int nsig, hipStream_t s);
 
 }  // namespace plss

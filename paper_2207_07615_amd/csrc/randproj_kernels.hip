@@ -11,7 +11,7 @@
 // Launch sequence of one iteration (every kernel returns early once the
 // solve is done):
 //   k_rp_sketch, k_rp_y, k_rp_gram, k_rp_sig, k_rp_solve, k_rp_p,
-//   k_spmv<RESID> (r -= A p, partial rho), k_rp_fin
+//   k_sspmv<RESID> or k_spmv<RESID> (r -= A p, partial rho), k_rp_fin
 #include "kernels.hpp"
 #include "randproj.hpp"
 
@@ -99,10 +99,27 @@ __global__ __launch_bounds__(256) void k_rp_y(const Desc* __restrict__ d, const 
   const int j = blockIdx.x * (256 / LPR) + threadIdx.x / LPR;
   if (j >= n || q >= rp) return;
   const double* __restrict__ tv = static_cast<const double*>(d->t_val);
+  const int* __restrict__ ti = d->t_idx;
   const double* __restrict__ S = rd->S;
   double acc = 0.0;
   const int e1 = d->t_ptr[j + 1];
-  for (int e = d->t_ptr[j]; e < e1; ++e) acc += tv[e] * S[(size_t)d->t_idx[e] * rp + q];
+  int e = d->t_ptr[j];
+  // eight entries at a time: indices, values and gathered rows of S all in
+  // flight before the first product (the sum keeps the entry order)
+  for (; e + 8 <= e1; e += 8) {
+    int c[8];
+    double v[8], sv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      c[u] = ti[e + u];
+      v[u] = tv[e + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sv[u] = S[(size_t)c[u] * rp + q];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u] * sv[u];
+  }
+  for (; e < e1; ++e) acc += tv[e] * S[(size_t)ti[e] * rp + q];
   rd->Y[(size_t)j * rp + q] = acc;
 }
 
@@ -241,7 +258,7 @@ __global__ __launch_bounds__(kPB) void k_rp_fin(const Desc* __restrict__ d, cons
   __shared__ double s_red[kPB / 64];
   State* st = d->st;
   if (st->final_done || st->done) return;
-  const double rho = bsum_array(d->part_rho, d->a_ntiles, s_red);
+  const double rho = bsum_array(d->part_rho, d->rho_cnt, s_red);
   if (threadIdx.x != 0) return;
   st->rho = rho;
   if (st->k_total < d->hist_len) d->hist[st->k_total] = sqrt(rho) * st->scale;
@@ -257,7 +274,7 @@ __global__ __launch_bounds__(kPB) void k_rp_fin(const Desc* __restrict__ d, cons
 }
 
 void launch_rp_step(const Desc* d, const RpDesc* rd, int rp, int m, int n, int AV, const int2* alist, int na,
-                    int ngram, int nsig, hipStream_t s) {
+                    bool striped, int ngram, int nsig, hipStream_t s) {
   const long long cnt = (long long)m * (rp / 4);
   const int gs = (int)std::min<long long>((cnt + 255) / 256, 16384);
   k_rp_sketch<<<gs, 256, 0, s>>>(d, rd);
@@ -272,7 +289,8 @@ void launch_rp_step(const Desc* d, const RpDesc* rd, int rp, int m, int n, int A
   k_rp_sig<<<nsig, 256, 0, s>>>(d, rd);
   k_rp_solve<<<1, kPB, 0, s>>>(d, rd);
   k_rp_p<<<std::min((n + 255) / 256, 8192), 256, 0, s>>>(d, rd);
-  launch_spmv(MODE_RESID, false, AV, d, alist, na, 0, s);
+  if (striped) launch_sspmv(MODE_RESID, false, d, alist, na, 0, s);
+  else launch_spmv(MODE_RESID, false, AV, d, alist, na, 0, s);
   k_rp_fin<<<1, kPB, 0, s>>>(d, rd);
   PLSS_HIP(hipGetLastError());
 }

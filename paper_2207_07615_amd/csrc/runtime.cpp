@@ -142,7 +142,7 @@ void auto_layout(long long m, long long n, long long nnz, bool f32, bool* a_stri
   if ((double)m * vb > (double)(3u << 20)) {
     const int R = auto_unit_rows(n, kMaxBlk, kRBT);
     const long long nu = (long long)kMaxBlk * ((n + R - 1) / R);
-    const long long S = (m / kMaxBlk + kSWT) / kSWT;
+    const long long S = (m / kMaxBlk + swt(f32)) / swt(f32);
     if (S <= kMaxStripes && nu >= 128 && (double)nu * ((double)m / kMaxBlk) * vb <= entry_bytes) *t_stripes = true;
   }
 }
@@ -311,8 +311,8 @@ void matrix_set_layout(plss_matrix* M, bool a_stripes, bool t_stripes, int unit_
       if (!M->t_striped || M->SB[0].unit_rows != R || M->SB[0].balanced != bal) {
         M->t_striped = false;
         for (int b = 0; b < M->nblk; ++b)
-          build_stripes(M->TB[b], M->rb[b], M->rb[b + 1] - M->rb[b], R, kRBT, bal, kSWT, kQmaxT, M->f32, M->SB[b],
-                        s);
+          build_stripes(M->TB[b], M->rb[b], M->rb[b + 1] - M->rb[b], R, kRBT, bal, swt(M->f32), kQmaxT, M->f32,
+                        M->SB[b], s);
       }
     } else {
       for (int b = 0; b < kMaxBlk; ++b) free_stripes(M->SB[b]);

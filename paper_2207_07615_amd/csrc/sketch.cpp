@@ -107,27 +107,37 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
     };
     hipEvent_t e0, e1;
     PLSS_HIP(hipEventCreate(&e0));
-    PLSS_HIP(hipEventCreate(&e1));
-    PLSS_HIP(hipEventRecord(e0, s));
-    outer_seq();
-    launch_col_init(d_desc, dsys, 1, s);
-    long long t = 0;
-    int chunk = o->chunk > 0 ? o->chunk : 16;
-    while (true) {
-      for (int c = 0; c < chunk; ++c, ++t) {
-        const bool resid = (d.sketch == 2) && (t % 2 == 0);
-        launch_sketch_step(d_desc, A->A.V, dla, (int)la.size(), dlt, (int)lt.size(), dlu, (int)lu.size(),
-                           dlw, (int)lw.size(), dsys, 1, resid, A->T.V, s);
-      }
-      PLSS_HIP(hipMemcpyAsync(h_state, d_state, sizeof(State), hipMemcpyDeviceToHost, s));
-      PLSS_HIP(hipStreamSynchronize(s));
-      if (h_state->done || h_state->final_done) break;
-      if (o->chunk <= 0) chunk = std::min(chunk * 2, 128);
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      throw DeviceError{};
     }
-    outer_seq();  // true residual of the final x
-    PLSS_HIP(hipMemcpyAsync(h_state, d_state, sizeof(State), hipMemcpyDeviceToHost, s));
-    PLSS_HIP(hipEventRecord(e1, s));
-    PLSS_HIP(hipEventSynchronize(e1));
+    try {
+      PLSS_HIP(hipEventRecord(e0, s));
+      outer_seq();
+      launch_col_init(d_desc, dsys, 1, s);
+      long long t = 0;
+      int chunk = o->chunk > 0 ? o->chunk : 16;
+      while (true) {
+        for (int c = 0; c < chunk; ++c, ++t) {
+          const bool resid = (d.sketch == 2) && (t % 2 == 0);
+          launch_sketch_step(d_desc, A->A.V, dla, (int)la.size(), dlt, (int)lt.size(), dlu, (int)lu.size(),
+                             dlw, (int)lw.size(), dsys, 1, resid, A->T.V, s);
+        }
+        PLSS_HIP(hipMemcpyAsync(h_state, d_state, sizeof(State), hipMemcpyDeviceToHost, s));
+        PLSS_HIP(hipStreamSynchronize(s));
+        if (h_state->done || h_state->final_done) break;
+        if (o->chunk <= 0) chunk = std::min(chunk * 2, 128);
+      }
+      outer_seq();  // true residual of the final x
+      PLSS_HIP(hipMemcpyAsync(h_state, d_state, sizeof(State), hipMemcpyDeviceToHost, s));
+      PLSS_HIP(hipEventRecord(e1, s));
+      PLSS_HIP(hipEventSynchronize(e1));
+    } catch (...) {
+      (void)hipStreamSynchronize(s);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      throw;
+    }
     float ms = 0;
     PLSS_HIP(hipEventElapsedTime(&ms, e0, e1));
     (void)hipEventDestroy(e0);
@@ -144,6 +154,7 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
     info->status = fs.final_done ? fs.final_status : fs.status;
     info->ms = ms;
   } catch (...) {
+    (void)hipStreamSynchronize(s);
     dfree(d_lists);
     dfree(d_state);
     dfree(d_desc);

@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kPW) void k_col_init(const Desc* __restrict__ D, co
   const Desc* d = D + sys[blockIdx.x];
   State* st = d->st;
   if (st->final_done || st->done || st->k != 0 || st->col != 0) return;
-  const double rho = bsum_array(d->part_rho, d->a_ntiles, s_red);
+  const double rho = bsum_array(d->part_rho, d->rho_cnt, s_red);
   if (threadIdx.x != 0) return;
   st->thr = st->tol_abs ? st->tol : st->tol * st->nb_out;
   st->scale = (st->tol_abs || st->nb_out == 0.0) ? 1.0 : 1.0 / st->nb_out;
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(kPW) void k_col_fin(const Desc* __restrict__ D, con
   double theta = 0.0, rho = 0.0;
   if (!skip) {
     theta = bsum_array(d->part_theta, d->u_nblk, s_red);
-    rho = bsum_array(d->part_rho, d->a_ntiles, s_red);
+    rho = bsum_array(d->part_rho, d->rho_cnt, s_red);
   }
   if (threadIdx.x != 0) return;
   st->col = t + 1;

@@ -449,7 +449,7 @@ void st_ysum(const double* ypart, int nblk, int n, double* y, hipStream_t s) {
 
 void launch_sspmv(int mode, bool f32, const Desc* d, const int2* list, int n, int transposed, hipStream_t s) {
   if (n <= 0) return;
-  constexpr int A1 = kSWA, A2 = kRBA, A3 = kQmaxA, T1 = kSWT, T2 = kRBT, T3 = kQmaxT;
+  constexpr int A1 = kSWA, A2 = kRBA, A3 = kQmaxA, T1 = kSWT, T2 = kRBT, T3 = kQmaxT, T1f = kSWT32;
   if (!f32) {
     switch (mode) {
       case MODE_RESID: k_sspmv<double, double, double, MODE_RESID, A1, A2, A3><<<n, kST, 0, s>>>(d, list, 0); break;
@@ -463,11 +463,13 @@ void launch_sspmv(int mode, bool f32, const Desc* d, const int2* list, int n, in
   } else {
     switch (mode) {
       case MODE_RESID: k_sspmv<float, float, float, MODE_RESID, A1, A2, A3><<<n, kST, 0, s>>>(d, list, 0); break;
-      case MODE_TRANSB: k_sspmv<float, float, float, MODE_TRANSB, T1, T2, T3><<<n, kST, 0, s>>>(d, list, 1); break;
+      case MODE_TRANSB: k_sspmv<float, float, float, MODE_TRANSB, T1f, T2, T3><<<n, kST, 0, s>>>(d, list, 1); break;
       case MODE_REFINE: k_sspmv<float, double, double, MODE_REFINE, A1, A2, A3><<<n, kST, 0, s>>>(d, list, 0); break;
       default:
-        if (transposed) k_sspmv<float, double, double, MODE_PLAIN, T1, T2, T3><<<n, kST, 0, s>>>(d, list, 1);
-        else k_sspmv<float, double, double, MODE_PLAIN, A1, A2, A3><<<n, kST, 0, s>>>(d, list, 0);
+        // the float64-accumulating plain product does not fit the float32
+        // stores of Aᵀ (their stripes are 8192 wide): callers use the tiles
+        if (transposed) throw InvalidArg{"plain transposed product on a float32 striped store"};
+        k_sspmv<float, double, double, MODE_PLAIN, A1, A2, A3><<<n, kST, 0, s>>>(d, list, 0);
         break;
     }
   }

@@ -94,3 +94,21 @@ def test_randproj_edge_cases(h):
             plss.solve(h, M, sysm.b, sketch="randproj", block=bad, tol=1e-8, maxit=10)
     with pytest.raises(plss.PlssError):
         plss.solve(h, matrix(h, sysm.A, "f32"), sysm.b, sketch="randproj", block=5, tol=1e-8, maxit=10)
+
+
+def test_randproj_on_striped_products(h):
+    """With a striped store of A (the layout of the large workload) the
+    product r -= A p and the initial and final residuals run on the stripes;
+    the iterates are the oracle's."""
+    import paper_2207_07615_amd as plss
+    say("randproj striped")
+    sysm = gen.large(m=60000, n=15000)
+    M = matrix(h, sysm.A)
+    lay = M.layout(a_stripes=True, t_stripes=True, unit_rows=512)
+    assert lay["a_stripes"]
+    for k in (1, 4):
+        x, info, hist = plss.solve(h, M, sysm.b, sketch="randproj", block=5, seed=9, tol=1e-300, maxit=k)
+        ref = RP.randproj(sysm.A, sysm.b, r=5, seed=9, tol=1e-300, maxit=k)
+        assert info["iters"] == k
+        assert rel(x, ref.x) <= 1e-12
+        assert abs(info["relres_true"] - ref.relres_true) <= 1e-12 * max(1.0, ref.relres_true)
