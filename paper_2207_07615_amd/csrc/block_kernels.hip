@@ -51,10 +51,9 @@ __device__ double bsum_array(const double* __restrict__ a, int n, double* s_tmp)
   return bsum(v, s_tmp);
 }
 
-// a_iᵀ a_l of two CSR rows (ascending column indices)
-__device__ double row_dot(const int* __restrict__ ptr, const int* __restrict__ idx, const double* __restrict__ val,
-                          int i, int l) {
-  int p = ptr[i], pe = ptr[i + 1], q = ptr[l], qe = ptr[l + 1];
+// a_iᵀ a_l of two sparse rows with ascending column indices: entries
+// [p, pe) and [q, qe) of (idx, val)
+__device__ double row_dot(const int* idx, const double* val, int p, int pe, int q, int qe) {
   double g = 0.0;
   while (p < pe && q < qe) {
     const int c1 = idx[p], c2 = idx[q];
@@ -115,6 +114,11 @@ __global__ __launch_bounds__(kPB) void k_blk_prep(const Desc* __restrict__ d, co
   __shared__ int s_keep[kBW];
   __shared__ int s_w, s_K, s_nblk, s_nk, s_stop;
   __shared__ double s_red[kPB / 64];
+  // the block's rows of A, staged for the sparse Gram entries when they fit
+  constexpr int kStage = 3072;
+  __shared__ int s_ridx[kStage];
+  __shared__ double s_rval[kStage];
+  __shared__ int s_roff[kBW + 1];
   State* st = d->st;
   BlkState* bs = bd->bs;
   if (st->final_done || st->done) return;
@@ -153,6 +157,26 @@ __global__ __launch_bounds__(kPB) void k_blk_prep(const Desc* __restrict__ d, co
     }
   }
   const double phi = res ? bsum_array(d->part_phi, d->t_ntiles, s_red) : 0.0;  // y_rᵀ y_r
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int o = 0;
+    for (int l = 0; l < w; ++l) {
+      s_roff[l] = o;
+      if (l >= res) o += d->a_ptr[s_rows[l] + 1] - d->a_ptr[s_rows[l]];
+    }
+    s_roff[w] = o;
+  }
+  __syncthreads();
+  const bool staged = s_roff[w] <= kStage;
+  if (staged) {
+    for (int l = res; l < w; ++l) {
+      const int b0 = d->a_ptr[s_rows[l]], len = s_roff[l + 1] - s_roff[l];
+      for (int e = threadIdx.x; e < len; e += kPB) {
+        s_ridx[s_roff[l] + e] = d->a_idx[b0 + e];
+        s_rval[s_roff[l] + e] = av[b0 + e];
+      }
+    }
+  }
   __syncthreads();
   // W = Zᵀ Y_new into Ug (row k = history column k)
   for (int e = threadIdx.x; e < K * w; e += kPB) {
@@ -212,12 +236,19 @@ __global__ __launch_bounds__(kPB) void k_blk_prep(const Desc* __restrict__ d, co
     if (l < res) {
       g = phi;
     } else if (a < res) {
-      const int i = s_rows[l];
       const double* __restrict__ y = static_cast<const double*>(d->y);
       g = 0.0;
-      for (int q = d->a_ptr[i]; q < d->a_ptr[i + 1]; ++q) g += y[d->a_idx[q]] * av[q];
+      if (staged) {
+        for (int q = s_roff[l]; q < s_roff[l + 1]; ++q) g += y[s_ridx[q]] * s_rval[q];
+      } else {
+        const int i = s_rows[l];
+        for (int q = d->a_ptr[i]; q < d->a_ptr[i + 1]; ++q) g += y[d->a_idx[q]] * av[q];
+      }
+    } else if (staged) {
+      g = row_dot(s_ridx, s_rval, s_roff[a], s_roff[a + 1], s_roff[l], s_roff[l + 1]);
     } else {
-      g = row_dot(d->a_ptr, d->a_idx, av, s_rows[a], s_rows[l]);
+      const int i = s_rows[a], k2 = s_rows[l];
+      g = row_dot(d->a_idx, av, d->a_ptr[i], d->a_ptr[i + 1], d->a_ptr[k2], d->a_ptr[k2 + 1]);
     }
     s_G[a][l] = g;
     s_G[l][a] = g;
