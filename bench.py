@@ -9,7 +9,9 @@ resident in HBM (torch device tensors) during the timed region.
 
 Reported: PLSS iterations/s (value), solves/s, algorithmic HBM GB/s of the
 iteration, the roofline of the dominant kernel (per-kernel HIP events on
-the library's stream during the timed region), the oracle timed on the host
+the library's stream during the timed region, around the phases of one
+iteration in eight so that the events barely slow the others), the oracle
+timed on the host
 on a bounded sample, and two more arms of the same system timed separately
 after the main region: float32 storage + float64 refinement, and PLSS W
 (W = diag(1/||A_{:,j}||), Section 4.1).

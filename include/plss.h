@@ -94,8 +94,11 @@ typedef struct {
   int64_t hist_cap;     /* identity/mixed/block: history columns kept before the
                            stored history is cleared (0: min(m, n, 256); at most
                            256 for identity/mixed, 1024 for the block sketches) */
-  int32_t chunk;        /* iterations per launch batch between host checks (0: auto) */
-  int32_t timing;       /* record per-kernel device times (see plss_kernel_times) */
+  int32_t chunk;        /* iterations per launch batch between host checks (0: auto;
+                           the residual sketch predicts it from the observed
+                           decrease of the residual, and takes at most 256) */
+  int32_t timing;       /* record per-kernel device times with events around the
+                           phases of one iteration in eight (see plss_kernel_times) */
   int32_t engine;       /* residual sketch: 0 = automatic, 1 = one launch per phase
                            (all CUs on the system), 2 = single workgroup: the whole
                            solve in one workgroup, vectors and row pointers in

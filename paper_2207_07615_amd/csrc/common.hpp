@@ -54,6 +54,10 @@ constexpr int kSWT = 2048, kRBT = 16384;
 // stripes, and their fixed costs, than at 2048.  The plain product, which
 // accumulates in float64, runs on the CSC tiles for these stores.
 constexpr int kSWT32 = 8192;
+// Float32 stores of A: the unit's row sums take 32 KB, so the stripes of the
+// float32 kernel can be as wide as kSWA32 (2 x 48 KB at 12288).
+constexpr int kSWA32 = 6144;
+inline int swa(bool f32) { return f32 ? kSWA32 : kSWA; }
 inline int swt(bool f32) { return f32 ? kSWT32 : kSWT; }
 constexpr int kSThreads = 1024;
 // most entries per lane in one window of a wave range (a window holds up to
@@ -61,6 +65,10 @@ constexpr int kSThreads = 1024;
 // A averages about 410 entries, one of Aᵀ about 270 (eight for A measured
 // slower than seven, though fewer ranges then take a second window).
 constexpr int kQmaxA = 7, kQmaxT = 6;
+// the same for float32 stores (an entry takes two registers instead of three)
+constexpr int kQmaxA32 = 7, kQmaxT32 = 6;
+inline int qa(bool f32) { return f32 ? kQmaxA32 : kQmaxA; }
+inline int qt(bool f32) { return f32 ? kQmaxT32 : kQmaxT; }
 constexpr int kMaxStripes = 8192;  // stripes per store (cursor table of the builder in LDS)
 constexpr size_t kSmallLds = 156 * 1024;  // LDS for r, p, y of a single-workgroup solve
 constexpr long long kSmallNnz = 1 << 18;  // automatic single-workgroup solves up to this many entries
@@ -80,7 +88,7 @@ struct StripeView {
   const int* wsp;              // 16 row-aligned wave starts per segment
   int nunits, S;
   int colbase, ncols;          // columns [colbase, colbase + ncols) of the gathered vector
-  int sw;                      // stripe width (kSWA, kSWT or kSWT32)
+  int sw;                      // stripe width (kSWA, kSWA32, kSWT or kSWT32)
 };
 
 struct State {

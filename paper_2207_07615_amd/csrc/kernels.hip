@@ -72,6 +72,53 @@ __device__ double big_sum_array(const double* __restrict__ a, int n, double* s_t
   return t;
 }
 
+// Fixed-order sums of four arrays by one workgroup of kRW threads, their
+// loads issued together (valid in thread 0): thread t adds elements
+// t, t + kRW, t + 2 kRW, ... of each array in turn, then the workgroup adds
+// the threads' sums wave by wave.  s_tmp: 4 x 16 doubles.
+__device__ double4 big_sums4(const double* __restrict__ a0, int n0, const double* __restrict__ a1, int n1,
+                             const double* __restrict__ a2, int n2, const double* __restrict__ a3, int n3,
+                             double* s_tmp) {
+  const int nmax = max(max(n0, n1), max(n2, n3));
+  double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+  // a loop taken at least once, so the arrays' addresses are not waited
+  // for behind a test of the counts
+  int i = threadIdx.x;
+  do {
+    const double e0 = i < n0 ? a0[i] : 0.0;
+    const double e1 = i < n1 ? a1[i] : 0.0;
+    const double e2 = i < n2 ? a2[i] : 0.0;
+    const double e3 = i < n3 ? a3[i] : 0.0;
+    v0 += e0;
+    v1 += e1;
+    v2 += e2;
+    v3 += e3;
+    i += kRW;
+  } while (i - (int)threadIdx.x < nmax);
+  v0 = wave_sum(v0);
+  v1 = wave_sum(v1);
+  v2 = wave_sum(v2);
+  v3 = wave_sum(v3);
+  constexpr int W = kRW / 64;
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    s_tmp[w] = v0;
+    s_tmp[W + w] = v1;
+    s_tmp[2 * W + w] = v2;
+    s_tmp[3 * W + w] = v3;
+  }
+  __syncthreads();
+  // thread a adds array a's wave sums in wave order
+  if (threadIdx.x < 4) {
+    const double* t = s_tmp + threadIdx.x * W;
+    double r = t[0];
+    for (int q = 1; q < W; ++q) r += t[q];
+    s_tmp[4 * W + threadIdx.x] = r;
+  }
+  __syncthreads();
+  return make_double4(s_tmp[4 * W], s_tmp[4 * W + 1], s_tmp[4 * W + 2], s_tmp[4 * W + 3]);
+}
+
 // Exclusive segmented scan across the workgroup of (f, v) pairs, where a
 // set flag starts a new segment after the element:
 //   incl_j = f_j ? v_j : incl_{j-1} + v_j,  result_j = incl_{j-1} (0 for j = 0).
@@ -461,18 +508,20 @@ __global__ __launch_bounds__(kWG) void k_start(const Desc* __restrict__ D, const
 
 // Algorithm 1: rho, stop test, phi, theta, beta, gamma (one workgroup per system).
 __global__ __launch_bounds__(kRW) void k_step(const Desc* __restrict__ D, const int* __restrict__ sys) {
-  __shared__ double s_red[kRW / 64];
+  __shared__ double s_red[4 * (kRW / 64) + 4];
   const Desc* d = D + sys[blockIdx.x];
   State* st = d->st;
-  if (st->final_done || st->done) return;
-  const double rho = big_sum_array(d->part_rho, d->rho_cnt, s_red);
-  const double phi = big_sum_array(d->part_phi, d->phi_cnt, s_red);
+  // the state's flags and the four partial sums at once: theta's partials
+  // are used only after the first update, those of ||c||^2 only before it
+  // (the other one is summed for nothing)
+  const int stopped = st->final_done | st->done;
   const long long k = st->k;
-  double theta = 0.0;
-  if (k > 0) theta = big_sum_array(d->part_theta, d->u_nblk, s_red);
-  double nbi = 0.0;
-  if (k == 0) nbi = big_sum_array(d->part_b, d->rho_cnt, s_red);
-  if (threadIdx.x != 0) return;
+  const double4 sums = big_sums4(d->part_rho, d->rho_cnt, d->part_phi, d->phi_cnt, d->part_theta, d->u_nblk,
+                                 d->part_b, d->rho_cnt, s_red);
+  if (threadIdx.x != 0 || stopped) return;
+  const double rho = sums.x, phi = sums.y;
+  const double theta = k > 0 ? sums.z : 0.0;
+  const double nbi = k == 0 ? sums.w : 0.0;
 
   if (k == 0) {
     // inner right-hand side norm and thresholds
@@ -537,27 +586,39 @@ __global__ __launch_bounds__(kWG) void k_update(const Desc* __restrict__ D, cons
   const int2 ent = list[blockIdx.x];
   const Desc* d = D + ent.x;
   const State* st = d->st;
-  if (st->final_done || st->done) return;
-  const double beta = st->beta, gamma = st->gamma;
-  const bool fresh = st->fresh != 0;
   Vec* __restrict__ p = static_cast<Vec*>(d->p);
   const Vec* __restrict__ y = static_cast<const Vec*>(d->y);
   double* __restrict__ x = d->x;
   const double* __restrict__ wi = d->wi;
   const int n = d->n;
   const int base = ent.y * (kWG * 4);
+  // the vectors are loaded beside the state (whose flags and scalars they
+  // do not depend on), so one round trip to memory precedes the arithmetic
+  double yv[4], pv[4], xv[4], wv[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = base + u * kWG + threadIdx.x;
+    const bool in = j < n;
+    yv[u] = in ? double(y[j]) : 0.0;
+    pv[u] = in ? double(p[j]) : 0.0;
+    xv[u] = in ? x[j] : 0.0;
+    wv[u] = (in && wi) ? wi[j] : 1.0;
+  }
+  if (st->final_done || st->done) return;
+  const double beta = st->beta, gamma = st->gamma;
+  const bool fresh = st->fresh != 0;
   double part = 0.0;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int j = base + u * kWG + threadIdx.x;
     if (j < n) {
-      const double w = wi ? wi[j] : 1.0;
-      const double wy = wi ? double(y[j]) / w : double(y[j]);
-      const double pn = fresh ? gamma * wy : beta * double(p[j]) + gamma * wy;
-      const Vec pv = Vec(pn);
-      p[j] = pv;
-      x[j] += double(pv);
-      part += double(pv) * double(pv) * w;
+      const double w = wv[u];
+      const double wy = wi ? yv[u] / w : yv[u];
+      const double pn = fresh ? gamma * wy : beta * pv[u] + gamma * wy;
+      const Vec pr = Vec(pn);
+      p[j] = pr;
+      x[j] = xv[u] + double(pr);
+      part += double(pr) * double(pr) * w;
     }
   }
   part = block_sum(part, s_red);
@@ -1054,26 +1115,33 @@ __global__ __launch_bounds__(kWG) void k_ycomb(const Desc* __restrict__ D, const
   const int2 ent = list[blockIdx.x];
   const Desc* d = D + ent.x;
   const State* st = d->st;
-  if (st->final_done || st->done || d->nblk <= 1) return;
   const int n = d->n, nb = d->nblk;
+  if (nb <= 1) return;
   Vec* __restrict__ y = static_cast<Vec*>(d->y);
   const Vec* __restrict__ yp = static_cast<const Vec*>(d->ypart);
+  const double* __restrict__ wi = d->wi;
   double part = 0.0;
   const int base = ent.y * (kWG * 4);
+  // every block's partials loaded first (beside the state's flags, which
+  // they do not depend on), then added in block order
+  Vec v[4][kMaxBlk];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = base + u * kWG + threadIdx.x;
+#pragma unroll
+    for (int b = 0; b < kMaxBlk; ++b) v[u][b] = (b < nb && j < n) ? yp[(size_t)b * n + j] : Vec(0);
+  }
+  if (st->final_done || st->done) return;
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int j = base + u * kWG + threadIdx.x;
     if (j < n) {
-      // all blocks' partials loaded first, then added in block order
-      Vec v[kMaxBlk];
+      Vec s = v[u][0];
 #pragma unroll
-      for (int b = 0; b < kMaxBlk; ++b) v[b] = b < nb ? yp[(size_t)b * n + j] : Vec(0);
-      Vec s = v[0];
-#pragma unroll
-      for (int b = 1; b < kMaxBlk; ++b) s = b < nb ? s + v[b] : s;
+      for (int b = 1; b < kMaxBlk; ++b) s = b < nb ? s + v[u][b] : s;
       y[j] = s;
       const double ds = double(s);
-      part += d->wi ? ds * ds / d->wi[j] : ds * ds;
+      part += wi ? ds * ds / wi[j] : ds * ds;
     }
   }
   part = block_sum(part, s_red);

@@ -136,7 +136,7 @@ void auto_layout(long long m, long long n, long long nnz, bool f32, bool* a_stri
   {
     const int R = auto_unit_rows(m, 1, kRBA);
     const long long nu = (m + R - 1) / R;
-    const long long S = (n + kSWA - 1) / kSWA;
+    const long long S = (n + swa(f32) - 1) / swa(f32);
     if (S <= kMaxStripes && nu >= 128 && (double)nu * (double)n * vb <= 0.75 * entry_bytes) *a_stripes = true;
   }
   if ((double)m * vb > (double)(3u << 20)) {
@@ -296,7 +296,7 @@ void matrix_set_layout(plss_matrix* M, bool a_stripes, bool t_stripes, int unit_
       const bool bal = unit_rows == 0;
       if (!M->a_striped || M->SA.unit_rows != R || M->SA.balanced != bal) {
         M->a_striped = false;
-        build_stripes(M->A, 0, (int)M->n, R, kRBA, bal, kSWA, kQmaxA, M->f32, M->SA, s);
+        build_stripes(M->A, 0, (int)M->n, R, kRBA, bal, swa(M->f32), qa(M->f32), M->f32, M->SA, s);
       }
     } else {
       free_stripes(M->SA);
@@ -311,7 +311,7 @@ void matrix_set_layout(plss_matrix* M, bool a_stripes, bool t_stripes, int unit_
       if (!M->t_striped || M->SB[0].unit_rows != R || M->SB[0].balanced != bal) {
         M->t_striped = false;
         for (int b = 0; b < M->nblk; ++b)
-          build_stripes(M->TB[b], M->rb[b], M->rb[b + 1] - M->rb[b], R, kRBT, bal, swt(M->f32), kQmaxT, M->f32,
+          build_stripes(M->TB[b], M->rb[b], M->rb[b + 1] - M->rb[b], R, kRBT, bal, swt(M->f32), qt(M->f32), M->f32,
                         M->SB[b], s);
       }
     } else {

@@ -432,6 +432,13 @@ void BatchRunner::build_lists(const std::vector<int>& active, hipStream_t s) {
   ws_.lists.build(items, s);
 }
 
+// most iterations between host checks; the phases of one iteration in
+// kTimeEvery carry timing events (iterations kTimeOffset, kTimeOffset +
+// kTimeEvery, ... of a chunk: never one that directly follows an outer
+// step, which comes before iterations that are multiples of 4)
+constexpr int kChunkMax = 256;
+constexpr int kTimeEvery = 8, kTimeOffset = 2;
+
 void BatchRunner::run(hipStream_t s, bool timing, int chunk_req) {
   const int ns = (int)items_.size();
   std::vector<int> active, small64, small32;
@@ -475,36 +482,58 @@ void BatchRunner::run(hipStream_t s, bool timing, int chunk_req) {
     const plss_matrix* M = runs_[i]->A;
     bytes_iter += (M->f32 ? 16.0 : 24.0) * M->nnz + 28.0 * M->m + 60.0 * M->n;
   }
-  // iterations per chunk: grow from a small first chunk (small systems finish
-  // early) towards ~4 ms of work between host checks
+  // Iterations per chunk (between host checks).  The first chunk is short
+  // (small systems finish early); after it, a system's observed decrease of
+  // ln ||r|| per update over the last chunk predicts the updates left to its
+  // stop test, and the next chunk covers the slowest prediction.  An
+  // iteration launched after a system stopped costs only early-exit
+  // launches; a chunk ended too soon costs one more host check.
   const double t_iter = bytes_iter / 4.0e12 + 20e-6;
-  int cmax = (int)std::min(128.0, std::max(8.0, 4e-3 / t_iter));
-  int chunk = chunk_req > 0 ? chunk_req : std::min(16, cmax);
-  const int outer_every = any_f32 ? 4 : 1 << 30;
+  const int cfirst = (int)std::min(16.0, std::max(4.0, 4e-3 / t_iter));
+  int chunk = chunk_req > 0 ? chunk_req : cfirst;
+  // float32 storage: the outer (refinement) step also runs every outer_every
+  // iterations inside a chunk, so an inner solve that stops between host
+  // checks is refined soon; often in a batch, where systems stop at
+  // different times and the last one sets the batch's length
+  const int outer_every = !any_f32 ? 1 << 30 : (ns > 1 ? 4 : 16);  // multiples of 4
   std::vector<hipEvent_t>& events_ = ws_.iter_events;
   if (timing && events_.empty()) {
-    events_.resize(5 * 128);
+    events_.resize(5 * (kChunkMax / kTimeEvery + 1));
     for (auto& e : events_) PLSS_HIP(hipEventCreate(&e));
   }
+  std::vector<double> lr_prev(ns, 0.0);
+  std::vector<long long> kt_prev(ns, -1), outer_prev(ns, -1), kt_chunk(ns, 0);
   const ListSet& lists_ = ws_.lists;
+  // the outer step ends every chunk, so it starts only the first: after it
+  // no running system is stopped and unrefined, and repeating it changes nothing
+  lists_.outer_seq(d_desc_, s);
   while (!active.empty()) {
-    lists_.outer_seq(d_desc_, s);
-    const int c = timing ? std::min(chunk, 128) : chunk;
+    const int c = std::min(chunk, kChunkMax);
+    // iterations timed: one in kTimeEvery, so the events barely slow the
+    // rest, and never one right after an outer step, whose product with A
+    // is skipped when it starts an inner solve
+    int ne = 0;
+    // updates of each system so far (h_state_ holds the last sync)
+    for (int i : active) kt_chunk[i] = h_state_[i].k_total;
     for (int it = 0; it < c; ++it) {
       if (it > 0 && it % outer_every == 0) lists_.outer_seq(d_desc_, s);
-      lists_.iteration(d_desc_, s, timing ? &events_[5 * it] : nullptr);
+      const bool tev = timing && it % kTimeEvery == kTimeOffset;
+      lists_.iteration(d_desc_, s, tev ? &events_[5 * ne++] : nullptr);
     }
     lists_.outer_seq(d_desc_, s);
     PLSS_HIP(hipMemcpyAsync(h_state_, d_state_, sizeof(State) * ns, hipMemcpyDeviceToHost, s));
     PLSS_HIP(hipStreamSynchronize(s));
-    if (timing) {
-      for (int it = 0; it < c; ++it) {
-        for (int q = 0; q < 4; ++q) {
-          float ms = 0;
-          PLSS_HIP(hipEventElapsedTime(&ms, events_[5 * it + q], events_[5 * it + q + 1]));
-          h_->kt_ms[q] += ms;
-          h_->kt_n[q] += 1;
-        }
+    // iterations that made an update: a system's updates are consecutive, so
+    // those of the chunk are its first (k_total advanced) ones; the launches
+    // after every system stopped only exit early and are not timed
+    long long live = 0;
+    for (int i : active) live = std::max(live, h_state_[i].k_total - kt_chunk[i]);
+    for (int it = 0; it < ne && kTimeOffset + kTimeEvery * it < live; ++it) {
+      for (int q = 0; q < 4; ++q) {
+        float ms = 0;
+        PLSS_HIP(hipEventElapsedTime(&ms, events_[5 * it + q], events_[5 * it + q + 1]));
+        h_->kt_ms[q] += ms;
+        h_->kt_n[q] += 1;
       }
     }
     std::vector<int> still;
@@ -514,7 +543,42 @@ void BatchRunner::run(hipStream_t s, bool timing, int chunk_req) {
       active.swap(still);
       if (!active.empty()) build_lists(active, s);
     }
-    if (chunk_req <= 0) chunk = std::min(cmax, chunk * 2);
+    // predicted updates left: the slowest system whose last chunk measured a
+    // decrease inside one inner solve
+    bool known = !active.empty();
+    double rem_max = 0.0;
+    for (int i : active) {
+      const State& st = h_state_[i];
+      const double lr = 0.5 * std::log(std::max(st.rho, 1e-300));
+      const long long dk = st.k_total - kt_prev[i];
+      if (kt_prev[i] >= 0 && st.outer == outer_prev[i] && !st.done && st.k > dk && dk >= 2 && st.thr > 0.0) {
+        const double rate = (lr - lr_prev[i]) / (double)dk;
+        if (rate < 0.0) {
+          double rem = (std::log(st.thr) - lr) / rate;
+          rem = std::min(rem, (double)(st.maxit - st.k_total));
+          rem_max = std::max(rem_max, rem);
+        } else {
+          known = false;
+        }
+      } else {
+        known = false;
+      }
+      kt_prev[i] = st.k_total;
+      lr_prev[i] = lr;
+      outer_prev[i] = st.outer;
+    }
+    if (chunk_req <= 0) {
+      if (known) {
+        // short predictions exactly (plus one), long ones by half: the
+        // decrease often speeds up as a solve goes on, so a long prediction
+        // tends to be high, and a chunk that ends early costs less than one
+        // that runs on past the stop
+        const double want = rem_max <= 16.0 ? std::ceil(rem_max) + 1.0 : std::ceil(0.5 * rem_max);
+        chunk = (int)std::min<double>(kChunkMax, std::max(2.0, want));
+      } else {
+        chunk = cfirst;
+      }
+    }
   }
   if (any_small) {
     // the single-workgroup systems' final states

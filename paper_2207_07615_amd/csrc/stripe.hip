@@ -209,7 +209,8 @@ template <class Val, class Vin, class Acc, int MODE, int SW, int RB, int QM>
 __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const int2* __restrict__ list,
                                                int transposed) {
   __shared__ __attribute__((aligned(16))) Acc s_x[2][SW];
-  __shared__ Acc s_acc[RB];
+  // float row sums: 64 spare words past the unit's rows (see sum_window)
+  __shared__ Acc s_acc[RB + (sizeof(Acc) == 4 ? 64 : 0)];
   // the epilogue's cross-wave partial sums reuse the slice buffers (no wave
   // reads them after the stripe loop's last barrier)
   double (*s_red)[kSWaves] = reinterpret_cast<double (*)[kSWaves]>(&s_x[0][0]);
@@ -223,13 +224,24 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
   const int2 ent = list[blockIdx.x];
   if (ent.y < 0) return;  // padding of an XCD-interleaved list
   const Desc* d = D + ent.x;
+  // The iteration's products (RESID, TRANSB) run far more often than they
+  // skip, so they read the state's flags beside the first loads of the
+  // product and leave only once those are issued: the flags' load then does
+  // not lengthen the chain of dependent loads before the stream starts.  A
+  // skipped launch reads a little of the store for nothing.
+  constexpr bool kLate = MODE == MODE_RESID || MODE == MODE_TRANSB;
+  bool skip = false;
   if (MODE != MODE_PLAIN) {
     const State* st = d->st;
     if (MODE == MODE_REFINE) {
       if (st->final_done || !st->done) return;
     } else {
-      if (st->final_done || st->done) return;
-      if (MODE == MODE_RESID && st->k == 0) return;
+      // all three read at once (no short-circuit: each test would wait for
+      // its own load before the next is issued)
+      const int fd = st->final_done, dn = st->done;
+      const long long kk = MODE == MODE_RESID ? st->k : 1;
+      skip = ((fd | dn) != 0) | (kk == 0);
+      if (!kLate && skip) return;
     }
   }
   const bool tb = MODE == MODE_TRANSB || (MODE == MODE_PLAIN && transposed);
@@ -281,6 +293,7 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
 
   for (int i = threadIdx.x; i < nr; i += kST) s_acc[i] = Acc(0);
   for (int j = threadIdx.x; j < SW; j += kST) s_x[0][j] = j < xlen ? Acc(gload(&x[j])) : Acc(0);
+  if (kLate && skip) return;  // the same for the whole workgroup
   __syncthreads();
 
   auto stripe = [&](int s, int& ws0, int& we0, const Ent<Val>* ce, int ws1, int we1, Ent<Val>* me) {
@@ -320,12 +333,12 @@ __global__ __launch_bounds__(kST) void k_sspmv(const Desc* __restrict__ D, const
       const int Q = range_q(we0 - ws0, QM);
       Acc wc = Acc(0);  // run open at the end of the previous window
       int wr = -1;
-      sum_window<Val, Acc, QM>(min(64 * Q, we0 - ws0), ce, xs, s_acc, wc, wr);
+      sum_window<Val, Acc, QM, RB>(min(64 * Q, we0 - ws0), ce, xs, s_acc, wc, wr);
       for (int base = ws0 + 64 * Q; base < we0; base += 64 * Q) {
         const int c = min(64 * Q, we0 - base);
         Ent<Val> ev[QM];
         load_window<Val, QM>(rec, base, c, ev);
-        sum_window<Val, Acc, QM>(c, ev, xs, s_acc, wc, wr);
+        sum_window<Val, Acc, QM, RB>(c, ev, xs, s_acc, wc, wr);
       }
       flush_open(s_acc, wc, wr);
     }
@@ -449,7 +462,8 @@ void st_ysum(const double* ypart, int nblk, int n, double* y, hipStream_t s) {
 
 void launch_sspmv(int mode, bool f32, const Desc* d, const int2* list, int n, int transposed, hipStream_t s) {
   if (n <= 0) return;
-  constexpr int A1 = kSWA, A2 = kRBA, A3 = kQmaxA, T1 = kSWT, T2 = kRBT, T3 = kQmaxT, T1f = kSWT32;
+  constexpr int A1 = kSWA, A2 = kRBA, A3 = kQmaxA, T1 = kSWT, T2 = kRBT, T3 = kQmaxT;
+  constexpr int A1f = kSWA32, A3f = kQmaxA32, T1f = kSWT32, T3f = kQmaxT32;
   if (!f32) {
     switch (mode) {
       case MODE_RESID: k_sspmv<double, double, double, MODE_RESID, A1, A2, A3><<<n, kST, 0, s>>>(d, list, 0); break;
@@ -462,14 +476,16 @@ void launch_sspmv(int mode, bool f32, const Desc* d, const int2* list, int n, in
     }
   } else {
     switch (mode) {
-      case MODE_RESID: k_sspmv<float, float, float, MODE_RESID, A1, A2, A3><<<n, kST, 0, s>>>(d, list, 0); break;
-      case MODE_TRANSB: k_sspmv<float, float, float, MODE_TRANSB, T1f, T2, T3><<<n, kST, 0, s>>>(d, list, 1); break;
-      case MODE_REFINE: k_sspmv<float, double, double, MODE_REFINE, A1, A2, A3><<<n, kST, 0, s>>>(d, list, 0); break;
+      case MODE_RESID: k_sspmv<float, float, float, MODE_RESID, A1f, A2, A3f><<<n, kST, 0, s>>>(d, list, 0); break;
+      case MODE_TRANSB: k_sspmv<float, float, float, MODE_TRANSB, T1f, T2, T3f><<<n, kST, 0, s>>>(d, list, 1); break;
+      case MODE_REFINE:
+        k_sspmv<float, double, double, MODE_REFINE, A1f, A2, A3f><<<n, kST, 0, s>>>(d, list, 0);
+        break;
       default:
         // the float64-accumulating plain product does not fit the float32
         // stores of Aᵀ (their stripes are 8192 wide): callers use the tiles
         if (transposed) throw InvalidArg{"plain transposed product on a float32 striped store"};
-        k_sspmv<float, double, double, MODE_PLAIN, A1, A2, A3><<<n, kST, 0, s>>>(d, list, 0);
+        k_sspmv<float, double, double, MODE_PLAIN, A1f, A2, A3f><<<n, kST, 0, s>>>(d, list, 0);
         break;
     }
   }

@@ -114,9 +114,17 @@ __device__ __forceinline__ void load_window(const unsigned* __restrict__ rec, in
 // not; after the range's last window the caller writes it (flush_open).
 // No global load is needed to find where that run ends.  On entry wr = -1
 // if nothing is carried.
-template <class Val, class Acc, int QM>
+//
+// Float sums (no LDS atomic add: see lds_add) batch the window's run ends:
+// every slot's row sum is read first, then all are written, so the wave
+// waits for LDS once per window instead of once per slot.  The rows a
+// window ends are distinct, so the reads see no write of the same window.
+// A slot without a run end reads and writes the lane's spare word
+// s_acc[RB + lane] instead (the kernel's s_acc has RB + 64 words).
+template <class Val, class Acc, int QM, int RB>
 __device__ __forceinline__ void sum_window(int c, const Ent<Val>* e, const Acc* __restrict__ xs, Acc* s_acc,
                                            Acc& wc, int& wr) {
+  constexpr bool kBatch = sizeof(Acc) == 4;
   const int lane = threadIdx.x & 63;
   const int Qw = (c + 63) >> 6, r = c - 64 * (Qw - 1);
   const int mine = lane < r ? Qw : Qw - 1;
@@ -146,13 +154,20 @@ __device__ __forceinline__ void sum_window(int c, const Ent<Val>* e, const Acc* 
   for (int q = 0; q < QM; ++q) prods[q] = Acc(vv[q]) * xs[pv[q] & 0xFFFFu];
   // slots past the lane's entries leave the state unchanged (selects, so the
   // wave runs the slots without branching)
+  int wrow[QM];  // batched run ends: row (or the spare word) and sum
+  Acc wval[QM];
 #pragma unroll
   for (int q = 0; q < QM; ++q) {
     const bool act = q < mine;
     const int rr = (int)(pv[q] >> 16);
     const bool brk = act && rr != cur;
     const bool ended = brk && cur >= 0;  // the run of `cur` ends before this entry
-    if (ended && hend) lds_add(&s_acc[cur], acc);
+    if constexpr (kBatch) {
+      wrow[q] = (ended && hend) ? cur : RB + lane;
+      wval[q] = acc;
+    } else {
+      if (ended && hend) lds_add(&s_acc[cur], acc);
+    }
     const bool first = ended && !hend;   // the lane's first run end waits for the carry
     fv = first ? acc : fv;
     fr = first ? cur : fr;
@@ -160,6 +175,13 @@ __device__ __forceinline__ void sum_window(int c, const Ent<Val>* e, const Acc* 
     const Acc sum = acc + prods[q];
     acc = brk ? prods[q] : (act ? sum : acc);
     cur = act ? rr : cur;
+  }
+  if constexpr (kBatch) {
+    Acc old[QM];
+#pragma unroll
+    for (int q = 0; q < QM; ++q) old[q] = s_acc[wrow[q]];
+#pragma unroll
+    for (int q = 0; q < QM; ++q) s_acc[wrow[q]] = old[q] + wval[q];
   }
   if (lane < last && nrow != cur) {  // the lane's final run ends inside the window
     if (!hend) {
