@@ -3,6 +3,7 @@
 #include "block.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -131,14 +132,24 @@ void block_solve(plss_handle* h, const plss_matrix* A, const double* b, const pl
       PLSS_HIP(hipEventRecord(e0, s));
       outer_seq();
       launch_col_init(d_desc, dsys, 1, s);
-      int chunk = o->chunk > 0 ? o->chunk : 8;
+      // block steps per chunk: 8, then predicted from the residual's
+      // decrease per block step (steps past the stop exit at once)
+      constexpr int kFirst = 8, kCap = 64;
+      int chunk = o->chunk > 0 ? o->chunk : kFirst;
+      double lr_prev = 0.0, steps_prev = -1.0;
       while (true) {
         for (int c = 0; c < chunk; ++c)
           launch_block_step(d_desc, d_bd, residual, lpr, A->T.V, dlt, A->T.ntiles, n, wblk, nparts, s);
         PLSS_HIP(hipMemcpyAsync(h_state, d_state, sizeof(State), hipMemcpyDeviceToHost, s));
         PLSS_HIP(hipStreamSynchronize(s));
         if (h_state->done || h_state->final_done) break;
-        if (o->chunk <= 0) chunk = std::min(chunk * 2, 64);
+        if (o->chunk <= 0) {
+          const State& st = *h_state;  // st.col counts the block steps
+          const double rem = steps_prev >= 0.0 ? steps_left(st.rho, st.thr, (double)st.col, lr_prev, steps_prev) : -1.0;
+          chunk = chunk_for(rem, kFirst, kCap);
+          lr_prev = 0.5 * std::log(std::max(st.rho, 1e-300));
+          steps_prev = (double)st.col;
+        }
       }
       outer_seq();  // true residual of the final x
       PLSS_HIP(hipMemcpyAsync(h_state, d_state, sizeof(State), hipMemcpyDeviceToHost, s));

@@ -4,6 +4,7 @@
 #include "multi.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -102,7 +103,13 @@ plss_status run_group(plss_handle* h, const plss_matrix* A, int ncols, const dou
     PLSS_HIP(hipEventCreate(&e1));
     PLSS_HIP(hipEventRecord(e0, s));
     outer_step();
-    int chunk = o->chunk > 0 ? o->chunk : 8;
+    // iterations per chunk: 8, then predicted from the residuals' decrease
+    // (the slowest unfinished column of the inner solve; iterations past
+    // the last column's stop exit at once)
+    constexpr int kFirst = 8, kCap = 64;
+    int chunk = o->chunk > 0 ? o->chunk : kFirst;
+    std::vector<double> lr_prev(ncols, 0.0), kt_prev(ncols, -1.0);
+    long long outer_prev = -1;
     const bool timing = o->timing != 0;
     std::vector<hipEvent_t> ev;
     if (timing) {
@@ -141,7 +148,24 @@ plss_status run_group(plss_handle* h, const plss_matrix* A, int ncols, const dou
         PLSS_HIP(hipStreamSynchronize(s));
         if (hst->all_done) break;
       }
-      if (o->chunk <= 0) chunk = std::min(chunk * 2, 64);
+      if (o->chunk <= 0) {
+        bool known = hst->outer == outer_prev;
+        double rem_max = 0.0;
+        for (int c = 0; c < ncols; ++c) {
+          if (hst->done[c]) continue;
+          const double rem = known && kt_prev[c] >= 0.0
+                                 ? steps_left(hst->rho[c], hst->thr[c], (double)hst->k_total[c], lr_prev[c], kt_prev[c])
+                                 : -1.0;
+          if (rem < 0.0) known = false;
+          else rem_max = std::max(rem_max, std::min(rem, (double)(hst->maxit - hst->k_total[c])));
+        }
+        chunk = chunk_for(known ? rem_max : -1.0, kFirst, kCap);
+        for (int c = 0; c < ncols; ++c) {
+          lr_prev[c] = 0.5 * std::log(std::max(hst->rho[c], 1e-300));
+          kt_prev[c] = hst->done[c] ? -1.0 : (double)hst->k_total[c];
+        }
+        outer_prev = hst->outer;
+      }
     }
     PLSS_HIP(hipEventRecord(e1, s));
     PLSS_HIP(hipEventSynchronize(e1));

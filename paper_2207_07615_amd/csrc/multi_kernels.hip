@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kMB) void k_spmm(const MDesc* __restrict__ d) {
   for (int i = row0 + slot; i < row1; i += NS) {
     Acc acc = Acc(0);
     const int b0 = ptr[i], b1 = ptr[i + 1];
-    if (col) {
+    if (live) {  // a finished column's sums are not used: no gathers for it
       // eight entries at a time: their indices, values and gathered rows
       // are all in flight before the first product (the sum keeps the
       // entry order)

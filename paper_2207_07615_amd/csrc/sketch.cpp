@@ -2,6 +2,7 @@
 #include "sketch.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <vector>
 
@@ -116,7 +117,11 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
       outer_seq();
       launch_col_init(d_desc, dsys, 1, s);
       long long t = 0;
-      int chunk = o->chunk > 0 ? o->chunk : 16;
+      // column steps per chunk: 16, then predicted from the residual's
+      // decrease per column examined (steps past the stop exit at once)
+      constexpr int kFirst = 16, kCap = 128;
+      int chunk = o->chunk > 0 ? o->chunk : kFirst;
+      double lr_prev = 0.0, col_prev = -1.0;
       while (true) {
         for (int c = 0; c < chunk; ++c, ++t) {
           const bool resid = (d.sketch == 2) && (t % 2 == 0);
@@ -126,7 +131,14 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
         PLSS_HIP(hipMemcpyAsync(h_state, d_state, sizeof(State), hipMemcpyDeviceToHost, s));
         PLSS_HIP(hipStreamSynchronize(s));
         if (h_state->done || h_state->final_done) break;
-        if (o->chunk <= 0) chunk = std::min(chunk * 2, 128);
+        if (o->chunk <= 0) {
+          const State& st = *h_state;
+          double rem = col_prev >= 0.0 ? steps_left(st.rho, st.thr, (double)st.col, lr_prev, col_prev) : -1.0;
+          if (rem >= 0.0 && st.max_cols > st.col) rem = std::min(rem, (double)(st.max_cols - st.col));
+          chunk = chunk_for(rem, kFirst, kCap);
+          lr_prev = 0.5 * std::log(std::max(st.rho, 1e-300));
+          col_prev = (double)st.col;
+        }
       }
       outer_seq();  // true residual of the final x
       PLSS_HIP(hipMemcpyAsync(h_state, d_state, sizeof(State), hipMemcpyDeviceToHost, s));

@@ -432,6 +432,21 @@ void BatchRunner::build_lists(const std::vector<int>& active, hipStream_t s) {
   ws_.lists.build(items, s);
 }
 
+double steps_left(double rho, double thr, double steps, double lr_prev, double steps_prev) {
+  const double ds = steps - steps_prev;
+  if (!(ds >= 2.0) || !(thr > 0.0)) return -1.0;
+  const double lr = 0.5 * std::log(std::max(rho, 1e-300));
+  const double rate = (lr - lr_prev) / ds;
+  if (!(rate < 0.0)) return -1.0;
+  return std::max(0.0, (std::log(thr) - lr) / rate);
+}
+
+int chunk_for(double rem, int unknown, int cap) {
+  if (rem < 0.0) return std::min(unknown, cap);
+  const double want = rem <= 16.0 ? std::ceil(rem) + 1.0 : std::ceil(0.5 * rem);
+  return (int)std::min<double>(cap, std::max(2.0, want));
+}
+
 // most iterations between host checks; the phases of one iteration in
 // kTimeEvery carry timing events (iterations kTimeOffset, kTimeOffset +
 // kTimeEvery, ... of a chunk: never one that directly follows an outer
@@ -549,36 +564,17 @@ void BatchRunner::run(hipStream_t s, bool timing, int chunk_req) {
     double rem_max = 0.0;
     for (int i : active) {
       const State& st = h_state_[i];
-      const double lr = 0.5 * std::log(std::max(st.rho, 1e-300));
       const long long dk = st.k_total - kt_prev[i];
-      if (kt_prev[i] >= 0 && st.outer == outer_prev[i] && !st.done && st.k > dk && dk >= 2 && st.thr > 0.0) {
-        const double rate = (lr - lr_prev[i]) / (double)dk;
-        if (rate < 0.0) {
-          double rem = (std::log(st.thr) - lr) / rate;
-          rem = std::min(rem, (double)(st.maxit - st.k_total));
-          rem_max = std::max(rem_max, rem);
-        } else {
-          known = false;
-        }
-      } else {
-        known = false;
-      }
+      double rem = -1.0;
+      if (kt_prev[i] >= 0 && st.outer == outer_prev[i] && !st.done && st.k > dk)
+        rem = steps_left(st.rho, st.thr, (double)st.k_total, lr_prev[i], (double)kt_prev[i]);
+      if (rem < 0.0) known = false;
+      else rem_max = std::max(rem_max, std::min(rem, (double)(st.maxit - st.k_total)));
       kt_prev[i] = st.k_total;
-      lr_prev[i] = lr;
+      lr_prev[i] = 0.5 * std::log(std::max(st.rho, 1e-300));
       outer_prev[i] = st.outer;
     }
-    if (chunk_req <= 0) {
-      if (known) {
-        // short predictions exactly (plus one), long ones by half: the
-        // decrease often speeds up as a solve goes on, so a long prediction
-        // tends to be high, and a chunk that ends early costs less than one
-        // that runs on past the stop
-        const double want = rem_max <= 16.0 ? std::ceil(rem_max) + 1.0 : std::ceil(0.5 * rem_max);
-        chunk = (int)std::min<double>(kChunkMax, std::max(2.0, want));
-      } else {
-        chunk = cfirst;
-      }
-    }
+    if (chunk_req <= 0) chunk = chunk_for(known ? rem_max : -1.0, cfirst, kChunkMax);
   }
   if (any_small) {
     // the single-workgroup systems' final states

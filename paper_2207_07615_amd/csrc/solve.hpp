@@ -10,6 +10,18 @@ namespace plss {
 
 void validate_opts(const plss_opts* o, bool f32);
 
+// Chunks of steps between host checks.  steps_left predicts how many more
+// steps a solve needs to reach its stop test sqrt(rho) <= thr from the
+// decrease of ln sqrt(rho) per step since the last check (lr_prev, at step
+// count steps_prev, both of the same inner solve); -1 when that is unknown
+// or not a decrease.  chunk_for turns the slowest prediction into the next
+// chunk: a short one exactly plus one, a long one by half (the decrease
+// often speeds up as a solve goes on, and a chunk that ends early costs one
+// more check, one that runs past the stop only early-exit launches), within
+// [2, cap]; `unknown` when there is no prediction.
+double steps_left(double rho, double thr, double steps, double lr_prev, double steps_prev);
+int chunk_for(double rem, int unknown, int cap);
+
 // Device buffers and descriptor of one system.
 struct SysRun {
   const plss_matrix* A = nullptr;
