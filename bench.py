@@ -145,29 +145,35 @@ def run_small(args):
     import paper_2207_07615_amd as plss
     import plss_inputs as gen
     from oracle import plss as O
+    import torch
     sysm = gen.small()
     A = sysm.A
     h = plss.Handle(0)
     M = plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n))
+    b_d = torch.from_numpy(sysm.b).to(torch.device("cuda:0"))  # b and x stay in HBM
+    torch.cuda.synchronize()
     kw = dict(tol=1e-8, maxit=1000)
     for _ in range(args.warmup):
-        plss.solve(h, M, sysm.b, **kw)
+        plss.solve(h, M, b_d, **kw)
     lat, its, dev = [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
         ts = time.perf_counter()
-        x, info, _ = plss.solve(h, M, sysm.b, **kw)
+        x, info, _ = plss.solve(h, M, b_d, **kw)
         lat.append(time.perf_counter() - ts)
         its.append(info["iters"])
         dev.append(info["ms"])
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    x = x.cpu().numpy()
     # the per-phase engine on the same system, for comparison
-    plss.solve(h, M, sysm.b, engine="multi", **kw)
+    plss.solve(h, M, b_d, engine="multi", **kw)
     tm = time.perf_counter()
     itm = 0
     for _ in range(args.steps):
-        _, im, _ = plss.solve(h, M, sysm.b, engine="multi", **kw)
+        _, im, _ = plss.solve(h, M, b_d, engine="multi", **kw)
         itm += im["iters"]
+    torch.cuda.synchronize()
     wm = time.perf_counter() - tm
     bm = bytes_model(A.m, A.n, A.nnz)
     dev_ms = sum(dev) / len(dev)
@@ -229,41 +235,57 @@ def run_underdet(args):
     import paper_2207_07615_amd as plss
     import plss_inputs as gen
     from oracle import plss as O
+    import torch
     sysm = gen.underdet()
     A = sysm.A
     h = plss.Handle(0)
     M = plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n))
-    kw = dict(sketch="mixed", tol=1e-8, maxit=2000, row_perm=sysm.perm, hist_cap=128)
+    # b, the row order and x stay in HBM (device tensors) in the timed region
+    gpu = torch.device("cuda:0")
+    b_d = torch.from_numpy(sysm.b).to(gpu)
+    perm_d = torch.from_numpy(sysm.perm).to(gpu)
+    torch.cuda.synchronize()
+    kw = dict(sketch="mixed", tol=1e-8, maxit=2000, row_perm=perm_d, hist_cap=128)
     for _ in range(args.warmup):
-        plss.solve(h, M, sysm.b, **kw)
+        plss.solve(h, M, b_d, **kw)
     its, dev, cols = [], [], []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        x, info, _ = plss.solve(h, M, sysm.b, **kw)
+        x, info, _ = plss.solve(h, M, b_d, **kw)
         its.append(info["iters"])
         dev.append(info["ms"])
         cols.append(info["outer_iters"])
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # the same solves handed host buffers (b and the row order copied in, x
+    # copied out on every call): the rate with the PCIe transfers
+    kwh = dict(kw, row_perm=sysm.perm)
+    th = time.perf_counter()
+    for _ in range(3):
+        plss.solve(h, M, sysm.b, **kwh)
+    host_ms = 1e3 * (time.perf_counter() - th) / 3
     # bytes of the columns of one solve: columns alternate residual / identity,
     # the history holds the updates so far (no skip, no clear at this size)
     nupd = its[-1]
     col_b = sum(column_bytes(A.m, A.n, A.nnz, t // 2, t % 2 == 0) for t in range(cols[-1]))
     # mixed blocks of 15 identity rows plus r (one MFMA tile of 16 columns)
-    kwb = dict(sketch="block_mixed", block=15, tol=1e-8, maxit=2000, row_perm=sysm.perm, hist_cap=256)
+    kwb = dict(sketch="block_mixed", block=15, tol=1e-8, maxit=2000, row_perm=perm_d, hist_cap=256)
     for _ in range(args.warmup):
-        plss.solve(h, M, sysm.b, **kwb)
+        plss.solve(h, M, b_d, **kwb)
     itb, devb = [], []
     t1 = time.perf_counter()
     for _ in range(args.steps):
-        xb, ib, _ = plss.solve(h, M, sysm.b, **kwb)
+        xb, ib, _ = plss.solve(h, M, b_d, **kwb)
         itb.append(ib["iters"])
         devb.append(ib["ms"])
+    torch.cuda.synchronize()
     wallb = time.perf_counter() - t1
     blk_b = sum(block_bytes(A.m, A.n, A.nnz, 16 * (t % 16), 16, True) for t in range(itb[-1]))
     t2 = time.perf_counter()
     ref = O.plss_columns(A, sysm.b, "mixed", perm=sysm.perm, tol=1e-300, maxit=8, hist_cap=128)
     tc = time.perf_counter() - t2
     x8, i8, _ = plss.solve(h, M, sysm.b, sketch="mixed", tol=1e-300, maxit=8, row_perm=sysm.perm, hist_cap=128)
+    x8 = np.asarray(x8)
     return base_line(METRIC, sum(its) / wall, "updates/s", args.steps, args.warmup, wall, "f64",
                      {"workload": "underdet: 200,000 x 1,000,000 CSR, 30 nnz/row, U(-1,1), mixed sketch "
                                   "(residual + identity columns), FP64, tol 1e-8",
@@ -271,6 +293,7 @@ def run_underdet(args):
                      solves_per_s=args.steps / wall, updates_per_solve=sum(its) / len(its),
                      columns_per_solve=sum(cols) / len(cols),
                      device_ms_per_solve=sum(dev) / len(dev),
+                     host_buffers_ms_per_solve=host_ms,
                      relres_true=info["relres_true"], status=info["status_name"],
                      roofline=aggregate_roofline(col_b * args.steps, wall, "whole solves (all column steps)"),
                      rel_err_vs_oracle_8_updates=float(np.linalg.norm(x8 - ref.x) / np.linalg.norm(ref.x)),
@@ -327,15 +350,21 @@ def run_batch(args):
         f"nnz total {sum(d[0].nnz for d in data)}")
     tol = 1e-8
     h = plss.Handle(0)
+    import torch
     mats = [plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n), storage="f32") for A, _, _ in data]
-    bs = [b for _, b, _ in data]
+    # right-hand sides and solutions stay in HBM (device tensors) in the timed regions
+    gpu = torch.device("cuda:0")
+    bs = [torch.from_numpy(b).to(gpu) for _, b, _ in data]
+    torch.cuda.synchronize()
     kw = dict(tol=tol, maxit=args.maxit_cap, refine=True, inner_tol=1e-4)
     plss.solve_batch(h, mats[:8], bs[:8], **kw)   # warm-up (code objects, workspace)
     plss.kernel_times(h)
     t1 = time.perf_counter()
     xs, infos = plss.solve_batch(h, mats, bs, timing=True, **kw)
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t1
     kms, kn = plss.kernel_times(h)
+    xs = [x.cpu().numpy() for x in xs]
     rr = [host_relres(d[0], d[1], x) for x, d in zip(xs, data)]
     ok = [i["status"] == 0 and r <= tol for i, r in zip(infos, rr)]
     errs = [float(np.linalg.norm(x - d[2]) / np.linalg.norm(d[2])) for x, d, c in zip(xs, data, ok) if c]
@@ -349,16 +378,19 @@ def run_batch(args):
     t_tune = time.perf_counter() - t_tune
     t1 = time.perf_counter()
     xs_t, infos_t = plss.solve_batch(h, mats, bs, **kw)
+    torch.cuda.synchronize()
     wall_t = time.perf_counter() - t1
-    ok_t = sum(1 for x, i, d in zip(xs_t, infos_t, data) if i["status"] == 0 and host_relres(d[0], d[1], x) <= tol)
+    ok_t = sum(1 for x, i, d in zip(xs_t, infos_t, data)
+               if i["status"] == 0 and host_relres(d[0], d[1], x.cpu().numpy()) <= tol)
     del mats
     # one system at a time, plain float64 Algorithm 1 on the same GPU
     m64 = [plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n)) for A, _, _ in data]
     plss.solve(h, m64[0], bs[0], tol=tol, maxit=args.maxit_cap)
     t2 = time.perf_counter()
     res64 = [plss.solve(h, M64, b, tol=tol, maxit=args.maxit_cap)[:2] for M64, b in zip(m64, bs)]
+    torch.cuda.synchronize()
     t_plain = time.perf_counter() - t2
-    ok64 = [i["status"] == 0 and host_relres(d[0], d[1], x) <= tol for (x, i), d in zip(res64, data)]
+    ok64 = [i["status"] == 0 and host_relres(d[0], d[1], x.cpu().numpy()) <= tol for (x, i), d in zip(res64, data)]
     del m64
     nok, nok64 = sum(ok), sum(ok64)
     return base_line(METRIC, nok / wall, "solves/s", 1, 0, wall, "f32+f64",
@@ -384,17 +416,25 @@ def run_multi(args):
     import numpy as np
     import paper_2207_07615_amd as plss
     import plss_inputs as gen
+    import torch
     A, B, X = gen.shared_multi_rhs(storage=np.float32)
     h = plss.Handle(0)
     M = plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n), storage="f32")
+    # the right-hand sides (row c of B_d is column c: B_d.t() is the m x nrhs
+    # block, column-major as the library takes it) and the solutions stay in HBM
+    gpu = torch.device("cuda:0")
+    B_d = torch.from_numpy(np.ascontiguousarray(B)).to(gpu)
+    torch.cuda.synchronize()
     kw = dict(tol=1e-8, maxit=5000, refine=True, inner_tol=1e-4)
     for _ in range(args.warmup):
-        plss.solve_multi(h, M, B.T, **kw)
+        plss.solve_multi(h, M, B_d.t(), **kw)
     plss.kernel_times(h)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        Xg, infos = plss.solve_multi(h, M, B.T, timing=True, **kw)
+        Xg, infos = plss.solve_multi(h, M, B_d.t(), timing=True, **kw)
+    torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    Xg = Xg.cpu().numpy()
     kms, kn = plss.kernel_times(h)
     nrhs = B.shape[0]
     # block bytes per iteration: matrix once for all columns (float32 values + int32 index)
@@ -406,7 +446,8 @@ def run_multi(args):
     M64 = plss.Matrix(h, A.row_ptr, A.col_idx, A.vals, shape=(A.m, A.n))
     t1 = time.perf_counter()
     for c in range(4):
-        plss.solve(h, M64, B[c], tol=1e-8, maxit=5000)
+        plss.solve(h, M64, B_d[c], tol=1e-8, maxit=5000)
+    torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t1) / 4 * nrhs
     return base_line(METRIC, args.steps * nrhs / wall, "solves/s", args.steps, args.warmup, wall, "f32+f64",
                      {"workload": "multi: shared 500,000 x 250,000 CSR, 20 nnz/row, 32 RHS block, "

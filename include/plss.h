@@ -133,8 +133,9 @@ void plss_opts_default(plss_opts* opts);
 
 /* Create a handle on GPU `device` (its own non-blocking stream).  The calls
  * on a handle are serialised and keep their device scratch on it between
- * calls, growing it as needed and never shrinking it: launch tables and
- * per-system scalars; for the identity and mixed sketches a history block of
+ * calls, growing it as needed and never shrinking it: launch tables,
+ * per-system scalars and vectors, a pinned state mirror; for the multi-RHS
+ * solves their dense blocks; for the identity and mixed sketches a history block of
  * about 8 (m + n) hist_cap bytes; for the block sketches about
  * 8 (m + n) hist_cap bytes too (hist_cap up to 1024); for the randomized
  * projection 8 (m + n) r bytes (r rounded up to 4).  The largest such block a

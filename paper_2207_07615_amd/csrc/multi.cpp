@@ -36,10 +36,14 @@ plss_status run_group(plss_handle* h, const plss_matrix* A, int ncols, const dou
   const size_t oXi = f32 ? take(8ull * n * W) : 0;
   const size_t oPr = take(8ull * na_blk * W), oPb = take(8ull * na_blk * W);
   const size_t oPp = take(8ull * nt_blk * W), oPt = take(8ull * nu_blk * W);
-  const size_t oBin = take(8ull * m * ncols);
+  // the right-hand sides in, then the solution out (n x ncols)
+  const size_t oBin = take(8ull * std::max(m, n) * ncols);
   const size_t oSt = take(sizeof(MState)), oD = take(sizeof(MDesc));
-  char* ar = static_cast<char*>(dmalloc(off));
-  MState* hst = nullptr;
+  // device and pinned memory from the handle's workspace (calls on a handle
+  // are serialised and synchronise before returning)
+  Workspace& ws = workspace(h);
+  char* ar = ws.dev_block(off);
+  MState* hst = reinterpret_cast<MState*>(ws.pin_block(sizeof(MState)));
   plss_status agg = PLSS_OK;
   try {
     MDesc d{};
@@ -90,7 +94,6 @@ plss_status run_group(plss_handle* h, const plss_matrix* A, int ncols, const dou
     st.tol_abs = o->tol_absolute ? 1 : 0;
     PLSS_HIP(hipMemcpyAsync(d.st, &st, sizeof(st), hipMemcpyHostToDevice, s));
     PLSS_HIP(hipMemcpyAsync(dd, &d, sizeof(d), hipMemcpyHostToDevice, s));
-    PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&hst), sizeof(MState), hipHostMallocDefault));
 
     auto outer_step = [&]() {
       launch_maxpy(dd, std::min(65536, (int)(((long long)n * W + 1023) / 1024)), s);
@@ -98,9 +101,7 @@ plss_status run_group(plss_handle* h, const plss_matrix* A, int ncols, const dou
       launch_mouter(dd, s);
       launch_mstart(f32, dd, na_blk, s);
     };
-    hipEvent_t e0, e1;
-    PLSS_HIP(hipEventCreate(&e0));
-    PLSS_HIP(hipEventCreate(&e1));
+    hipEvent_t e0 = ws.t0, e1 = ws.t1;
     PLSS_HIP(hipEventRecord(e0, s));
     outer_step();
     // iterations per chunk: 8, then predicted from the residuals' decrease
@@ -111,34 +112,55 @@ plss_status run_group(plss_handle* h, const plss_matrix* A, int ncols, const dou
     std::vector<double> lr_prev(ncols, 0.0), kt_prev(ncols, -1.0);
     long long outer_prev = -1;
     const bool timing = o->timing != 0;
-    std::vector<hipEvent_t> ev;
-    if (timing) {
-      ev.resize(5);
-      for (auto& e : ev) PLSS_HIP(hipEventCreate(&e));
-    }
+    // per-phase timing events (only with opts.timing) around the phases of
+    // one iteration in eight (iterations 2, 10, ... of a chunk), read after
+    // the chunk's state copy; destroyed on every exit
+    constexpr int kTimeEvery = 8, kTimeOffset = 2;
+    struct Events {
+      std::vector<hipEvent_t> v;
+      ~Events() {
+        for (auto e : v) (void)hipEventDestroy(e);
+      }
+    } evs;
+    std::vector<hipEvent_t>& ev = evs.v;
+    std::vector<long long> kt_chunk(ncols, 0);  // updates of each column before the chunk
     while (true) {
+      const int nsamp = chunk > kTimeOffset ? (chunk - kTimeOffset + kTimeEvery - 1) / kTimeEvery : 0;
+      while (timing && (int)ev.size() < 5 * nsamp) {
+        hipEvent_t e;
+        PLSS_HIP(hipEventCreate(&e));
+        ev.push_back(e);
+      }
+      int ne = 0;
       for (int c = 0; c < chunk; ++c) {
-        if (timing) PLSS_HIP(hipEventRecord(ev[0], s));
+        const hipEvent_t* e = (timing && c % kTimeEvery == kTimeOffset) ? &ev[5 * ne++] : nullptr;
+        if (e) PLSS_HIP(hipEventRecord(e[0], s));
         launch_spmm(MMODE_RESID, f32, W, dd, na_blk, s);
-        if (timing) PLSS_HIP(hipEventRecord(ev[1], s));
+        if (e) PLSS_HIP(hipEventRecord(e[1], s));
         launch_spmm(MMODE_TRANS, f32, W, dd, nt_blk, s);
-        if (timing) PLSS_HIP(hipEventRecord(ev[2], s));
+        if (e) PLSS_HIP(hipEventRecord(e[2], s));
         launch_mstep(dd, s);
-        if (timing) PLSS_HIP(hipEventRecord(ev[3], s));
+        if (e) PLSS_HIP(hipEventRecord(e[3], s));
         launch_mupdate(f32, dd, nu_blk, s);
-        if (timing) {
-          PLSS_HIP(hipEventRecord(ev[4], s));
-          PLSS_HIP(hipEventSynchronize(ev[4]));
+        if (e) PLSS_HIP(hipEventRecord(e[4], s));
+      }
+      PLSS_HIP(hipMemcpyAsync(hst, d.st, sizeof(MState), hipMemcpyDeviceToHost, s));
+      PLSS_HIP(hipStreamSynchronize(s));
+      if (timing) {
+        // iterations in which some column made an update: the first `live`
+        // of the chunk (a column's updates are consecutive); later ones only
+        // exit early and are not counted
+        long long live = 0;
+        for (int c = 0; c < ncols; ++c) live = std::max(live, hst->k_total[c] - kt_chunk[c]);
+        for (int it = 0; it < ne && kTimeOffset + kTimeEvery * it < live; ++it) {
           for (int q = 0; q < 4; ++q) {
             float ms = 0;
-            PLSS_HIP(hipEventElapsedTime(&ms, ev[q], ev[q + 1]));
+            PLSS_HIP(hipEventElapsedTime(&ms, ev[5 * it + q], ev[5 * it + q + 1]));
             h->kt_ms[q] += ms;
             h->kt_n[q] += 1;
           }
         }
       }
-      PLSS_HIP(hipMemcpyAsync(hst, d.st, sizeof(MState), hipMemcpyDeviceToHost, s));
-      PLSS_HIP(hipStreamSynchronize(s));
       if (hst->all_done) break;
       bool all_inner = true;
       for (int c = 0; c < ncols; ++c) all_inner &= (hst->done[c] != 0);
@@ -166,26 +188,17 @@ plss_status run_group(plss_handle* h, const plss_matrix* A, int ncols, const dou
         }
         outer_prev = hst->outer;
       }
+      for (int c = 0; c < ncols; ++c) kt_chunk[c] = hst->k_total[c];
     }
     PLSS_HIP(hipEventRecord(e1, s));
     PLSS_HIP(hipEventSynchronize(e1));
     float ms = 0;
     PLSS_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    for (auto e : ev) (void)hipEventDestroy(e);
     // solution: row-major padded -> caller's column-major block
-    double* tmp = reinterpret_cast<double*>(ar + oBin);  // reuse (n x ncols fits if n <= m)
-    double* out = tmp;
-    char* extra = nullptr;
-    if ((size_t)n * ncols > (size_t)m * ncols) {
-      extra = static_cast<char*>(dmalloc(8ull * n * ncols));
-      out = reinterpret_cast<double*>(extra);
-    }
+    double* out = reinterpret_cast<double*>(ar + oBin);
     launch_transpose_out(d.X, n, ncols, W, out, s);
     PLSS_HIP(hipMemcpyAsync(Xcm, out, 8ull * n * ncols, hipMemcpyDefault, s));
     PLSS_HIP(hipStreamSynchronize(s));
-    dfree(extra);
     for (int c = 0; c < ncols; ++c) {
       plss_info& inf = info[c];
       inf.iters = hst->k_total[c];
@@ -197,12 +210,9 @@ plss_status run_group(plss_handle* h, const plss_matrix* A, int ncols, const dou
       if (agg == PLSS_OK && inf.status != PLSS_OK) agg = (plss_status)inf.status;
     }
   } catch (...) {
-    dfree(ar);
-    if (hst) (void)hipHostFree(hst);
+    (void)hipStreamSynchronize(s);
     throw;
   }
-  dfree(ar);
-  (void)hipHostFree(hst);
   return agg;
 }
 }  // namespace

@@ -28,17 +28,23 @@ void randproj_solve(plss_handle* h, const plss_matrix* A, const double* b, const
   const int ngram = std::max(1, std::min(512, (n + 255) / 256));
   const int nsig = (m + kRpRows - 1) / kRpRows;
 
-  State* d_state = static_cast<State*>(dmalloc(sizeof(State)));
-  Desc* d_desc = static_cast<Desc*>(dmalloc(sizeof(Desc)));
+  // the products with A use the striped store when the matrix has one (the
+  // partials of rho then come per unit); the system's arena, state,
+  // descriptor, list and pinned state mirror come from the handle's
+  // workspace (calls on a handle are serialised and synchronise before
+  // returning)
+  const bool as = A->a_striped;
+  const int na = as ? A->SA.nunits : A->A.ntiles;
+  Workspace& ws = workspace(h);
+  const long long hist_len = std::min<long long>(o->maxit + 2, 1LL << 22);
+  const Workspace::Call cm = ws.call_block(SysRun::arena_bytes(A, o, hist_len, true), sizeof(int2) * na + sizeof(int));
+  State* d_state = cm.d_state;
+  Desc* d_desc = cm.d_desc;
+  State* h_state = cm.h_state;
   SysRun run;
-  char* d_lists = nullptr;
-  State* h_state = nullptr;
   try {
-    // the products with A use the striped store when the matrix has one (the
-    // partials of rho then come per unit)
     run.use_stripes = true;
-    const bool as = A->a_striped;
-    run.setup(A, b, o, std::min<long long>(o->maxit + 2, 1LL << 22), d_state, nullptr);
+    run.setup(A, b, o, hist_len, d_state, cm.arena);
     run.upload(b, nullptr, nullptr, s);
     size_t off = 0;
     const size_t oS = off; off = up(off + 8 * (size_t)m * rp);
@@ -67,15 +73,13 @@ void randproj_solve(plss_handle* h, const plss_matrix* A, const double* b, const
     PLSS_HIP(hipMemcpyAsync(d_desc, &d, sizeof(Desc), hipMemcpyHostToDevice, s));
     PLSS_HIP(hipMemcpyAsync(d_state, &st, sizeof(State), hipMemcpyHostToDevice, s));
     // the A list: units of the striped store, or the CSR tile groups
-    const int na = as ? A->SA.nunits : A->A.ntiles;
     std::vector<int2> all;
     for (int t = 0; t < na; ++t) all.push_back(make_int2(0, t));
-    d_lists = static_cast<char*>(dmalloc(sizeof(int2) * all.size() + 64));
+    char* d_lists = cm.lists;
     int2* dla = reinterpret_cast<int2*>(d_lists);
     int* dsys = reinterpret_cast<int*>(dla + na);
     PLSS_HIP(hipMemcpyAsync(d_lists, all.data(), sizeof(int2) * all.size(), hipMemcpyHostToDevice, s));
     PLSS_HIP(hipMemsetAsync(dsys, 0, sizeof(int), s));
-    PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_state), sizeof(State), hipHostMallocDefault));
 
     auto outer_seq = [&]() {
       if (as) launch_sspmv(MODE_REFINE, false, d_desc, dla, na, 0, s);
@@ -83,10 +87,8 @@ void randproj_solve(plss_handle* h, const plss_matrix* A, const double* b, const
       launch_outer(d_desc, dsys, 1, s);
       launch_start(false, d_desc, dla, na, s);
     };
-    hipEvent_t e0, e1;
-    PLSS_HIP(hipEventCreate(&e0));
-    PLSS_HIP(hipEventCreate(&e1));
-    try {
+    hipEvent_t e0 = ws.t0, e1 = ws.t1;
+    {
       PLSS_HIP(hipEventRecord(e0, s));
       outer_seq();
       launch_col_init(d_desc, dsys, 1, s);
@@ -103,16 +105,9 @@ void randproj_solve(plss_handle* h, const plss_matrix* A, const double* b, const
       PLSS_HIP(hipMemcpyAsync(h_state, d_state, sizeof(State), hipMemcpyDeviceToHost, s));
       PLSS_HIP(hipEventRecord(e1, s));
       PLSS_HIP(hipEventSynchronize(e1));
-    } catch (...) {
-      (void)hipStreamSynchronize(s);
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      throw;
     }
     float ms = 0;
     PLSS_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     const State& fs = *h_state;
     PLSS_HIP(hipMemcpyAsync(x, run.desc.xo, 8 * (size_t)n, hipMemcpyDefault, s));
     const long long nh = std::min<long long>({hist_cap_out, fs.k_total + 1, run.hist_len});
@@ -126,16 +121,8 @@ void randproj_solve(plss_handle* h, const plss_matrix* A, const double* b, const
     info->ms = ms;
   } catch (...) {
     (void)hipStreamSynchronize(s);
-    dfree(d_lists);
-    dfree(d_state);
-    dfree(d_desc);
-    if (h_state) (void)hipHostFree(h_state);
     throw;
   }
-  dfree(d_lists);
-  dfree(d_state);
-  dfree(d_desc);
-  (void)hipHostFree(h_state);
 }
 
 }  // namespace plss

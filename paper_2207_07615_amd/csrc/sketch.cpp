@@ -37,17 +37,23 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
     for (int i = 0; i < m; ++i) perm[i] = i;
   }
 
-  State* d_state = static_cast<State*>(dmalloc(sizeof(State)));
-  Desc* d_desc = static_cast<Desc*>(dmalloc(sizeof(Desc)));
+  // the system's arena, state, descriptor, lists and pinned state mirror
+  // come from the handle's workspace (calls on a handle are serialised and
+  // synchronise before returning)
+  Workspace& ws = workspace(h);
+  const long long hist_len = std::min<long long>(o->maxit + 2, 1LL << 22);
+  const int wblk = (m + 1023) / 1024, u_nblk = (n + 1023) / 1024;
+  const size_t nl = (size_t)A->A.ntiles + A->T.ntiles + u_nblk + wblk;
+  const Workspace::Call cm = ws.call_block(SysRun::arena_bytes(A, o, hist_len, false), sizeof(int2) * nl + sizeof(int));
+  State* d_state = cm.d_state;
+  Desc* d_desc = cm.d_desc;
+  State* h_state = cm.h_state;
   SysRun run;
   char* extra = nullptr;
-  char* d_lists = nullptr;
-  State* h_state = nullptr;
   try {
     run.use_stripes = false;  // the one-column steps use the tile partition of the partials
-    run.setup(A, b, o, std::min<long long>(o->maxit + 2, 1LL << 22), d_state, nullptr);
+    run.setup(A, b, o, hist_len, d_state, cm.arena);
     run.upload(b, nullptr, nullptr, s);
-    const int wblk = (m + 1023) / 1024;
     // history and scratch: P (n x cap), AP (m x cap), Θ, c, partial w, dense row, order
     size_t off = 0;
     const size_t oP = off; off = up(off + 8 * (size_t)n * cap);
@@ -85,8 +91,7 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
     for (int t = 0; t < A->T.ntiles; ++t) lt.push_back(make_int2(0, t));
     for (int t = 0; t < run.u_nblk; ++t) lu.push_back(make_int2(0, t));
     for (int t = 0; t < wblk; ++t) lw.push_back(make_int2(0, t));
-    const size_t nl = la.size() + lt.size() + lu.size() + lw.size();
-    d_lists = static_cast<char*>(dmalloc(sizeof(int2) * nl + 64));
+    char* d_lists = cm.lists;
     int2* dla = reinterpret_cast<int2*>(d_lists);
     int2* dlt = dla + la.size();
     int2* dlu = dlt + lt.size();
@@ -97,22 +102,17 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
     all.insert(all.end(), lt.begin(), lt.end());
     all.insert(all.end(), lu.begin(), lu.end());
     all.insert(all.end(), lw.begin(), lw.end());
+    if (all.size() != nl) throw DeviceError{};  // the lists' space was sized from the same counts
     PLSS_HIP(hipMemcpyAsync(d_lists, all.data(), sizeof(int2) * nl, hipMemcpyHostToDevice, s));
     PLSS_HIP(hipMemsetAsync(dsys, 0, sizeof(int), s));
-    PLSS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_state), sizeof(State), hipHostMallocDefault));
 
     auto outer_seq = [&]() {
       launch_spmv(MODE_REFINE, false, A->A.V, d_desc, dla, (int)la.size(), 0, s);
       launch_outer(d_desc, dsys, 1, s);
       launch_start(false, d_desc, dla, (int)la.size(), s);
     };
-    hipEvent_t e0, e1;
-    PLSS_HIP(hipEventCreate(&e0));
-    if (hipEventCreate(&e1) != hipSuccess) {
-      (void)hipEventDestroy(e0);
-      throw DeviceError{};
-    }
-    try {
+    hipEvent_t e0 = ws.t0, e1 = ws.t1;
+    {
       PLSS_HIP(hipEventRecord(e0, s));
       outer_seq();
       launch_col_init(d_desc, dsys, 1, s);
@@ -144,16 +144,9 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
       PLSS_HIP(hipMemcpyAsync(h_state, d_state, sizeof(State), hipMemcpyDeviceToHost, s));
       PLSS_HIP(hipEventRecord(e1, s));
       PLSS_HIP(hipEventSynchronize(e1));
-    } catch (...) {
-      (void)hipStreamSynchronize(s);
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      throw;
     }
     float ms = 0;
     PLSS_HIP(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     const State& fs = *h_state;
     PLSS_HIP(hipMemcpyAsync(x, run.desc.xo, 8 * (size_t)n, hipMemcpyDefault, s));
     const long long nh = std::min<long long>({hist_cap_out, fs.k_total + 1, run.hist_len});
@@ -167,16 +160,8 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
     info->ms = ms;
   } catch (...) {
     (void)hipStreamSynchronize(s);
-    dfree(d_lists);
-    dfree(d_state);
-    dfree(d_desc);
-    if (h_state) (void)hipHostFree(h_state);
     throw;
   }
-  dfree(d_lists);
-  dfree(d_state);
-  dfree(d_desc);
-  (void)hipHostFree(h_state);
 }
 
 }  // namespace plss

@@ -221,6 +221,19 @@ char* Workspace::hist_block(size_t bytes) {
   return hist;
 }
 
+Workspace::Call Workspace::call_block(size_t arena_bytes, size_t list_bytes) {
+  auto up = [](size_t v) { return (v + 255) / 256 * 256; };
+  const size_t o_st = up(arena_bytes), o_d = up(o_st + sizeof(State)), o_l = up(o_d + sizeof(Desc));
+  char* dv = dev_block(o_l + list_bytes + 64);
+  Call c;
+  c.arena = dv;
+  c.d_state = reinterpret_cast<State*>(dv + o_st);
+  c.d_desc = reinterpret_cast<Desc*>(dv + o_d);
+  c.lists = dv + o_l;
+  c.h_state = reinterpret_cast<State*>(pin_block(sizeof(State)));
+  return c;
+}
+
 Workspace::~Workspace() {
   if (aux) (void)hipStreamSynchronize(aux);
   dfree(dev);

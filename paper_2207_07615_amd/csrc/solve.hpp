@@ -87,6 +87,17 @@ struct Workspace {
   char* dev_block(size_t bytes);
   char* pin_block(size_t bytes);
   char* hist_block(size_t bytes);
+  // One call's device memory in the blocks above: a system's arena, its
+  // State and Desc, list_bytes of launch lists; and a pinned State mirror
+  // (for the sketch, block and projection solves, which run one system).
+  struct Call {
+    char* arena;
+    State* d_state;
+    Desc* d_desc;
+    char* lists;
+    State* h_state;
+  };
+  Call call_block(size_t arena_bytes, size_t list_bytes);
   ~Workspace();
 };
 Workspace& workspace(plss_handle* h);
