@@ -148,8 +148,11 @@ plss_status plss_destroy(plss_handle* h);
 /* Upload A and build its device store once: CSR with int32 pointers and the
  * CSC copy (rows ascending inside every column) used for the products with
  * Aᵀ (Algorithm 1's y = Aᵀ r), values in `storage` precision, and the tile
- * tables of both.  Errors: EINVAL for a malformed CSR or nnz >= 2^31,
- * ENOMEM. */
+ * tables of both.  The first identity or mixed sketch solve on a matrix whose
+ * n float64 entries exceed 3 MB adds a copy of A split into 8 column blocks
+ * (one per XCD, equal entry counts) for its products A p; it stays with the
+ * matrix (plss_matrix_info counts it).  Errors: EINVAL for a malformed CSR or
+ * nnz >= 2^31, ENOMEM. */
 plss_status plss_matrix_create(plss_handle* h, const plss_csr* A, plss_dtype storage,
                                plss_matrix** out);
 plss_status plss_matrix_destroy(plss_matrix* A);

@@ -35,6 +35,7 @@ enum SpmvMode : int {
   MODE_PLAIN = 3,   // out <- A x (float64 in/out)
   MODE_AP = 4,      // ap <- A p ; r <- r - ap ; partial rho          (Section 7 storage of A p)
   MODE_TRANSB = 5,  // ypart[b] <- A_bᵀ r_b for row block b (XCD-local gather of r)
+  MODE_APB = 6,     // appart[b] <- A_b p for column block b (XCD-local gather of p; Section 7 A p)
 };
 
 constexpr int kMaxBlk = 8;         // row blocks of the transposed store (one per XCD)
@@ -155,6 +156,14 @@ struct Desc {
   const int* tb_tile[kMaxBlk];
   const int* tb_grp[kMaxBlk];
   void* ypart;                 // nblk x n block products (Vec)
+  // column-blocked CSR: block b holds the entries of columns [cb[b], cb[b+1])
+  int cnblk;                   // 1: products with A use the CSR above
+  const int* cb_ptr[kMaxBlk];
+  const int* cb_idx[kMaxBlk];
+  const void* cb_val[kMaxBlk];
+  const int* cb_tile[kMaxBlk];
+  const int* cb_grp[kMaxBlk];
+  double* appart;              // cnblk x m block products of A p (identity / mixed sketches)
   int phi_cnt;                 // partials of phi (t_ntiles, or u_nblk when blocked)
   // striped stores (used instead of the tiles when set)
   int a_striped;               // products with A (r update, refinement residual)

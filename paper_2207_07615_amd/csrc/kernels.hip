@@ -159,7 +159,7 @@ __device__ __forceinline__ bool spmv_skip(const State* st) {
   if (MODE == MODE_TRANSB) return st->final_done || st->done;
   if (st->final_done || st->done) return true;
   if (MODE == MODE_RESID) return st->k == 0;
-  if (MODE == MODE_AP) return st->skip != 0;
+  if (MODE == MODE_AP || MODE == MODE_APB) return st->skip != 0;
   return false;
 }
 
@@ -207,29 +207,34 @@ __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
   __shared__ int s_off[kWaves][TW + 1];     // row offsets of the tile
   __shared__ double s_wp[2][kWaves];
 
+  constexpr bool kBlk = MODE == MODE_TRANSB || MODE == MODE_APB;  // one block of an XCD-interleaved list
   const int2 ent = list[blockIdx.x];
-  if (MODE == MODE_TRANSB && ent.y < 0) return;  // padding of the XCD-interleaved list
+  if (kBlk && ent.y < 0) return;  // padding of the XCD-interleaved list
   const Desc* d = D + ent.x;
   const State* st = d->st;
   if (spmv_skip<MODE>(st)) return;
 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const bool tr = (MODE == MODE_TRANS) || (MODE == MODE_PLAIN && transpose);
-  const int blk = (MODE == MODE_TRANSB) ? (ent.y >> 24) : 0;
-  const int gi = (MODE == MODE_TRANSB) ? (ent.y & 0xFFFFFF) : ent.y;
-  const int* __restrict__ ptr = MODE == MODE_TRANSB ? d->tb_ptr[blk] : (tr ? d->t_ptr : d->a_ptr);
-  const int* __restrict__ idx = MODE == MODE_TRANSB ? d->tb_idx[blk] : (tr ? d->t_idx : d->a_idx);
-  const Val* __restrict__ val =
-      static_cast<const Val*>(MODE == MODE_TRANSB ? d->tb_val[blk] : (tr ? d->t_val : d->a_val));
-  const int* __restrict__ tile = MODE == MODE_TRANSB ? d->tb_tile[blk] : (tr ? d->t_tile : d->a_tile);
-  const int* __restrict__ grp = MODE == MODE_TRANSB ? d->tb_grp[blk] : (tr ? d->t_grp : d->a_grp);
+  const int blk = kBlk ? (ent.y >> 24) : 0;
+  const int gi = kBlk ? (ent.y & 0xFFFFFF) : ent.y;
+  const int* __restrict__ ptr =
+      MODE == MODE_TRANSB ? d->tb_ptr[blk] : (MODE == MODE_APB ? d->cb_ptr[blk] : (tr ? d->t_ptr : d->a_ptr));
+  const int* __restrict__ idx =
+      MODE == MODE_TRANSB ? d->tb_idx[blk] : (MODE == MODE_APB ? d->cb_idx[blk] : (tr ? d->t_idx : d->a_idx));
+  const Val* __restrict__ val = static_cast<const Val*>(
+      MODE == MODE_TRANSB ? d->tb_val[blk] : (MODE == MODE_APB ? d->cb_val[blk] : (tr ? d->t_val : d->a_val)));
+  const int* __restrict__ tile =
+      MODE == MODE_TRANSB ? d->tb_tile[blk] : (MODE == MODE_APB ? d->cb_tile[blk] : (tr ? d->t_tile : d->a_tile));
+  const int* __restrict__ grp =
+      MODE == MODE_TRANSB ? d->tb_grp[blk] : (MODE == MODE_APB ? d->cb_grp[blk] : (tr ? d->t_grp : d->a_grp));
 
   const Vin* __restrict__ xin;
   if (MODE == MODE_RESID) xin = static_cast<const Vin*>(d->p);
   else if (MODE == MODE_TRANS || MODE == MODE_TRANSB) xin = static_cast<const Vin*>(d->r);
   else if (MODE == MODE_REFINE) xin = reinterpret_cast<const Vin*>(d->xo);
   else if (MODE == MODE_PLAIN) xin = static_cast<const Vin*>(d->p);
-  else xin = reinterpret_cast<const Vin*>(d->P + (size_t)st->kh * d->n);
+  else xin = reinterpret_cast<const Vin*>(d->P + (size_t)st->kh * d->n);  // AP, APB: the new column of P
 
   double part = 0.0, part2 = 0.0;
 
@@ -255,6 +260,8 @@ __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
     } else if (MODE == MODE_TRANSB) {
       using Vec = Vin;
       static_cast<Vec*>(d->ypart)[(size_t)blk * d->n + i] = Vec(s);
+    } else if (MODE == MODE_APB) {
+      d->appart[(size_t)blk * d->m + i] = double(s);
     } else if (MODE == MODE_REFINE) {
       double bi = d->b[i];
       double ri = bi - double(s);
@@ -370,7 +377,7 @@ __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
     }
   }
 
-  if (MODE == MODE_PLAIN || MODE == MODE_TRANSB) return;
+  if (MODE == MODE_PLAIN || kBlk) return;
   part = wave_sum(part);
   if (MODE == MODE_REFINE) part2 = wave_sum(part2);
   if (lane == 0) {
@@ -896,6 +903,7 @@ void launch_spmv(int mode, bool f32, int V, const Desc* d, const int2* list, int
       case MODE_PLAIN: spmv_v<double, double, double, MODE_PLAIN>(V, d, list, n, transpose, s); break;
       case MODE_AP: spmv_v<double, double, double, MODE_AP>(V, d, list, n, 0, s); break;
       case MODE_TRANSB: spmv_v<double, double, double, MODE_TRANSB>(V, d, list, n, 1, s); break;
+      case MODE_APB: spmv_v<double, double, double, MODE_APB>(V, d, list, n, 0, s); break;
     }
   } else {
     switch (mode) {
@@ -1146,6 +1154,48 @@ __global__ __launch_bounds__(kWG) void k_ycomb(const Desc* __restrict__ D, const
   }
   part = block_sum(part, s_red);
   if (threadIdx.x == 0) d->part_phi[ent.y] = part;
+}
+
+// A p from its column-block products (identity and mixed sketches): for the
+// rows of one CSR tile group, ap_i = sum over blocks of appart[b][i] in block
+// order, then the step of MODE_AP: AP column kh <- ap, r <- r - ap, partial
+// rho per group (the same partition as the unblocked product's partials).
+__global__ __launch_bounds__(kWG) void k_apcomb(const Desc* __restrict__ D, const int2* __restrict__ list) {
+  __shared__ double s_red[kWaves];
+  const int2 ent = list[blockIdx.x];
+  const Desc* d = D + ent.x;
+  const State* st = d->st;
+  if (st->final_done || st->done || st->skip) return;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int m = d->m, nb = d->cnblk;
+  const double* __restrict__ ap = d->appart;
+  double* __restrict__ r = static_cast<double*>(d->r);
+  double* __restrict__ APk = d->AP + (size_t)st->kh * m;
+  double part = 0.0;
+  const int wt = d->a_grp[ent.y * kWaves + w];
+  if (wt >= 0) {
+    const int r0 = d->a_tile[wt], r1 = d->a_tile[wt + 1];
+    for (int i = r0 + lane; i < r1; i += 64) {
+      double v[kMaxBlk];
+#pragma unroll
+      for (int b = 0; b < kMaxBlk; ++b) v[b] = b < nb ? ap[(size_t)b * m + i] : 0.0;
+      double sum = v[0];
+#pragma unroll
+      for (int b = 1; b < kMaxBlk; ++b) sum = b < nb ? sum + v[b] : sum;
+      const double rn = r[i] - sum;
+      r[i] = rn;
+      APk[i] = sum;
+      part += rn * rn;
+    }
+  }
+  part = block_sum(part, s_red);
+  if (threadIdx.x == 0) d->part_rho[ent.y] = part;
+}
+
+void launch_apcomb(const Desc* d, const int2* alist, int n, hipStream_t s) {
+  if (n <= 0) return;
+  k_apcomb<<<n, kWG, 0, s>>>(d, alist);
+  PLSS_HIP(hipGetLastError());
 }
 
 // counts and per-block pointer arrays (bptr: nblk x (n+1), relative to each block)

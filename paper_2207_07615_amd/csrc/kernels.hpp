@@ -26,7 +26,7 @@ void ptr64_to_32(const long long* src, int n1, int* dst, hipStream_t s);
 void launch_col_init(const Desc* d, const int* sys, int ns, hipStream_t s);
 void launch_sketch_step(const Desc* d, int V, const int2* alist, int na, const int2* tlist, int nt,
                         const int2* ulist, int nu, const int2* wlist, int nw, const int* sys, int ns,
-                        bool residual_column, int VT, hipStream_t s);
+                        bool residual_column, int VT, const int2* cblist, int ncb, int VB, hipStream_t s);
 
 }  // namespace plss
 
@@ -59,6 +59,8 @@ void st_split(const unsigned* pk, const int* d_seg, long long nseg, int* d_wsp, 
 void st_interleave(const unsigned* pk, const void* val, bool f32, const int* d_seg, const int* d_wsp, long long nseg,
                    int qmax, unsigned* rec, hipStream_t s);
 void st_ysum(const double* ypart, int nblk, int n, double* y, hipStream_t s);
+// A p from the column-block products (MODE_APB) over the CSR tile groups of alist
+void launch_apcomb(const Desc* d, const int2* alist, int n, hipStream_t s);
 void launch_sspmv(int mode, bool f32, const Desc* d, const int2* list, int n, int transposed, hipStream_t s);
 // exclusive scan of n counts into out[0..n] (work: (n + 1023) / 1024 + 1 long longs)
 void scan_counts(const int* cnt, int n, int* out, void* work, hipStream_t s);

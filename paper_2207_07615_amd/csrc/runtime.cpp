@@ -283,6 +283,7 @@ static void recount_bytes(plss_matrix* M) {
   size_t b = (size_t)nnz * (vsz + 4) * (M->nblk > 1 ? 3 : 2) + sizeof(int) * (size_t)(m + n + 2) +
              sizeof(int) * (size_t)(M->A.ntiles + M->T.ntiles + 2) +
              (M->nblk > 1 ? sizeof(int) * (size_t)M->nblk * (n + 1) : 0);
+  if (M->cnblk > 1) b += (size_t)nnz * (vsz + 4) + sizeof(int) * (size_t)M->cnblk * (m + 1);
   b += M->SA.bytes;
   for (int q = 0; q < kMaxBlk; ++q) b += M->SB[q].bytes;
   M->bytes = b;
@@ -451,9 +452,15 @@ void matrix_destroy(plss_matrix* M) {
     dfree(d.tile);
     dfree(d.grp);
     free_stripes(M->SB[b]);
+    PlssDir& c = M->CB[b];
+    dfree(c.idx);
+    dfree(c.val);
+    dfree(c.tile);
+    dfree(c.grp);
   }
   free_stripes(M->SA);
   dfree(M->tb_ptr_all);
+  dfree(M->cb_ptr_all);
   delete M;
 }
 
@@ -513,6 +520,77 @@ void build_row_blocks(plss_matrix* M, hipStream_t s, bool force) {
   dfree(d_rb);
   dfree(d_cnt);
   dfree(work);
+}
+
+// Column blocks of A: when the gathered vector of a product with A (n
+// float64 entries) is larger than about 3 MB it does not stay in one XCD's
+// 4 MB L2; splitting the columns into 8 blocks of equal nnz gives every XCD
+// a slice that does.  Block b holds, row by row, the entries of its columns
+// (a contiguous sub-segment of each CSR row: column indices ascend).
+void build_col_blocks(plss_matrix* M, hipStream_t s) {
+  const size_t vb = M->f32 ? 4 : 8;
+  const long long m = M->m, n = M->n, nnz = M->nnz;
+  if (M->cnblk > 1 || (size_t)n * 8 <= (3u << 20) || nnz < 8 * 64) return;
+  const int nb = kMaxBlk;
+  // column boundaries balancing the entries (the CSC pointers count them)
+  const std::vector<int>& cp = M->T.h_ptr;
+  int cbnd[kMaxBlk + 1];
+  cbnd[0] = 0;
+  int j = 0;
+  for (int b = 1; b < nb; ++b) {
+    const long long target = nnz * b / nb;
+    while (j < n && cp[j] < target) ++j;
+    cbnd[b] = j;
+  }
+  cbnd[nb] = (int)n;
+  int* d_cb = static_cast<int*>(dmalloc(sizeof(int) * (nb + 1)));
+  int* d_cnt = nullptr;
+  void* work = nullptr;
+  PlssDir CB[kMaxBlk];
+  int* ptr_all = nullptr;
+  try {
+    d_cnt = static_cast<int*>(dmalloc(sizeof(int) * (size_t)nb * m));
+    work = dmalloc(sizeof(long long) * ((size_t)(m + 1023) / 1024 + 64));
+    ptr_all = static_cast<int*>(dmalloc(sizeof(int) * (size_t)nb * (m + 1)));
+    PLSS_HIP(hipMemcpyAsync(d_cb, cbnd, sizeof(int) * (nb + 1), hipMemcpyHostToDevice, s));
+    blk_build(M->A.ptr, M->A.idx, (int)m, d_cb, nb, d_cnt, ptr_all, work, s);
+    std::vector<int> hp((size_t)nb * (m + 1));
+    PLSS_HIP(hipMemcpyAsync(hp.data(), ptr_all, sizeof(int) * hp.size(), hipMemcpyDeviceToHost, s));
+    PLSS_HIP(hipStreamSynchronize(s));
+    for (int b = 0; b < nb; ++b) {
+      PlssDir& d = CB[b];
+      d.nrows = (int)m;
+      d.ncols = (int)n;
+      d.h_ptr.assign(hp.begin() + (size_t)b * (m + 1), hp.begin() + (size_t)(b + 1) * (m + 1));
+      const long long nz = d.h_ptr[m];
+      d.ptr = ptr_all + (size_t)b * (m + 1);
+      d.idx = static_cast<int*>(dmalloc(sizeof(int) * std::max<long long>(nz, 1)));
+      d.val = dmalloc(vb * std::max<long long>(nz, 1));
+      blk_copy(M->A.ptr, M->A.idx, M->A.val, M->f32, (int)m, b, ptr_all, d.idx, d.val, s);
+      set_tiles(d, M->A.V, s);
+    }
+    PLSS_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    for (auto& d : CB) {
+      dfree(d.idx);
+      dfree(d.val);
+      dfree(d.tile);
+      dfree(d.grp);
+    }
+    dfree(ptr_all);
+    dfree(d_cb);
+    dfree(d_cnt);
+    dfree(work);
+    throw;
+  }
+  dfree(d_cb);
+  dfree(d_cnt);
+  dfree(work);
+  for (int b = 0; b < nb; ++b) M->CB[b] = std::move(CB[b]);
+  std::memcpy(M->cbnd, cbnd, sizeof(cbnd));
+  M->cb_ptr_all = ptr_all;
+  M->cnblk = nb;
+  recount_bytes(M);
 }
 
 void handle_release(plss_handle* h) {

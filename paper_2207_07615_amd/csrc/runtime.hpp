@@ -67,6 +67,13 @@ struct plss_matrix {
   int rb[plss::kMaxBlk + 1] = {0};
   PlssDir TB[plss::kMaxBlk];
   int* tb_ptr_all = nullptr;   // nblk x (n+1) pointers shared by the blocks
+  // column-blocked copy of A (one block of columns per XCD) for the products
+  // with A whose gathered vector does not fit one XCD's L2 (the identity and
+  // mixed sketches' A p); built on first use, cnblk = 1 means none
+  int cnblk = 1;
+  int cbnd[plss::kMaxBlk + 1] = {0};
+  PlssDir CB[plss::kMaxBlk];
+  int* cb_ptr_all = nullptr;   // cnblk x (m+1) pointers shared by the blocks
   // striped stores: SA for products with A, SB[b] for row block b of Aᵀ
   bool a_striped = false, t_striped = false;
   PlssStripes SA;
@@ -92,6 +99,9 @@ plss_matrix* matrix_create(plss_handle* h, const plss_csr* A, plss_dtype storage
 void matrix_destroy(plss_matrix* A);
 void handle_release(plss_handle* h);  // drop one reference; frees a closed handle at zero
 void build_row_blocks(plss_matrix* M, hipStream_t s, bool force = false);
+// Column blocks of A, when the gathered vector of a product with A (n
+// float64 entries) exceeds about 3 MB; a no-op once built or when it fits.
+void build_col_blocks(plss_matrix* M, hipStream_t s);
 size_t matrix_footprint(long long m, long long n, long long nnz, bool f32);
 
 // Striped layout: build or drop the stores (unit_rows 0 = from the shape).

@@ -37,13 +37,22 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
     for (int i = 0; i < m; ++i) perm[i] = i;
   }
 
+  // column blocks of A for the product A p when the new column of P does
+  // not fit one XCD's L2 (built once per matrix, on its first sketch solve;
+  // calls on the matrix's handle are serialised)
+  build_col_blocks(const_cast<plss_matrix*>(A), s);
+  const int cnb = A->cnblk;
+  int qcb = 0;  // tile groups of the largest column block
+  for (int b = 0; b < cnb && cnb > 1; ++b) qcb = std::max(qcb, A->CB[b].ntiles);
+  const size_t ncbl = cnb > 1 ? (size_t)kMaxBlk * qcb : 0;
+
   // the system's arena, state, descriptor, lists and pinned state mirror
   // come from the handle's workspace (calls on a handle are serialised and
   // synchronise before returning)
   Workspace& ws = workspace(h);
   const long long hist_len = std::min<long long>(o->maxit + 2, 1LL << 22);
   const int wblk = (m + 1023) / 1024, u_nblk = (n + 1023) / 1024;
-  const size_t nl = (size_t)A->A.ntiles + A->T.ntiles + u_nblk + wblk;
+  const size_t nl = (size_t)A->A.ntiles + A->T.ntiles + u_nblk + wblk + ncbl;
   const Workspace::Call cm = ws.call_block(SysRun::arena_bytes(A, o, hist_len, false), sizeof(int2) * nl + sizeof(int));
   State* d_state = cm.d_state;
   Desc* d_desc = cm.d_desc;
@@ -63,6 +72,7 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
     const size_t oPw = off; off = up(off + 8 * (size_t)cap * wblk);
     const size_t oDn = off; off = up(off + 8 * (size_t)n);
     const size_t oPm = off; off = up(off + 4 * (size_t)m);
+    const size_t oAb = off; off = up(off + (cnb > 1 ? 8 * (size_t)m * cnb : 0));
     // kept by the handle between calls (they are serialised by its mutex and
     // synchronise before returning); nothing in it is read before this call
     // writes it, except the dense row, cleared here
@@ -78,6 +88,17 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
     d.wblk = wblk;
     d.dense = reinterpret_cast<double*>(extra + oDn);
     d.perm = reinterpret_cast<const int*>(extra + oPm);
+    d.cnblk = cnb;
+    if (cnb > 1) {
+      for (int b = 0; b < cnb; ++b) {
+        d.cb_ptr[b] = A->CB[b].ptr;
+        d.cb_idx[b] = A->CB[b].idx;
+        d.cb_val[b] = A->CB[b].val;
+        d.cb_tile[b] = A->CB[b].tile;
+        d.cb_grp[b] = A->CB[b].grp;
+      }
+      d.appart = reinterpret_cast<double*>(extra + oAb);
+    }
     d.sketch = o->sketch == PLSS_SKETCH_IDENTITY ? 1 : 2;
     State st = run.st0;
     st.hist_cap = cap;
@@ -91,17 +112,25 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
     for (int t = 0; t < A->T.ntiles; ++t) lt.push_back(make_int2(0, t));
     for (int t = 0; t < run.u_nblk; ++t) lu.push_back(make_int2(0, t));
     for (int t = 0; t < wblk; ++t) lw.push_back(make_int2(0, t));
+    // column-block tile groups, group q of block b at position 8 q + b so
+    // that block b's groups run on XCD b (-1: padding)
+    std::vector<int2> lc;
+    for (int q = 0; q < qcb && cnb > 1; ++q)
+      for (int b = 0; b < kMaxBlk; ++b)
+        lc.push_back(make_int2(0, (b < cnb && q < A->CB[b].ntiles) ? ((b << 24) | q) : -1));
     char* d_lists = cm.lists;
     int2* dla = reinterpret_cast<int2*>(d_lists);
     int2* dlt = dla + la.size();
     int2* dlu = dlt + lt.size();
     int2* dlw = dlu + lu.size();
-    int* dsys = reinterpret_cast<int*>(dlw + lw.size());
+    int2* dlc = dlw + lw.size();
+    int* dsys = reinterpret_cast<int*>(dlc + lc.size());
     std::vector<int2> all;
     all.insert(all.end(), la.begin(), la.end());
     all.insert(all.end(), lt.begin(), lt.end());
     all.insert(all.end(), lu.begin(), lu.end());
     all.insert(all.end(), lw.begin(), lw.end());
+    all.insert(all.end(), lc.begin(), lc.end());
     if (all.size() != nl) throw DeviceError{};  // the lists' space was sized from the same counts
     PLSS_HIP(hipMemcpyAsync(d_lists, all.data(), sizeof(int2) * nl, hipMemcpyHostToDevice, s));
     PLSS_HIP(hipMemsetAsync(dsys, 0, sizeof(int), s));
@@ -126,7 +155,8 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
         for (int c = 0; c < chunk; ++c, ++t) {
           const bool resid = (d.sketch == 2) && (t % 2 == 0);
           launch_sketch_step(d_desc, A->A.V, dla, (int)la.size(), dlt, (int)lt.size(), dlu, (int)lu.size(),
-                             dlw, (int)lw.size(), dsys, 1, resid, A->T.V, s);
+                             dlw, (int)lw.size(), dsys, 1, resid, A->T.V, dlc, (int)lc.size(),
+                             cnb > 1 ? A->CB[0].V : A->A.V, s);
         }
         PLSS_HIP(hipMemcpyAsync(h_state, d_state, sizeof(State), hipMemcpyDeviceToHost, s));
         PLSS_HIP(hipStreamSynchronize(s));

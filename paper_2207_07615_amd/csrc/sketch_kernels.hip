@@ -279,14 +279,20 @@ void launch_col_init(const Desc* d, const int* sys, int ns, hipStream_t s) {
 
 void launch_sketch_step(const Desc* d, int V, const int2* alist, int na, const int2* tlist, int nt,
                         const int2* ulist, int nu, const int2* wlist, int nw, const int* sys, int ns,
-                        bool residual_column, int VT, hipStream_t s) {
+                        bool residual_column, int VT, const int2* cblist, int ncb, int VB, hipStream_t s) {
   if (residual_column) {
     launch_spmv(MODE_TRANS, false, VT, d, tlist, nt, 1, s);
     k_gemvt<<<nw, kPW, 0, s>>>(d, wlist);
   }
   k_col_prep<<<ns, kPW, 0, s>>>(d, sys);
   k_gemv<<<nu, kWG, 0, s>>>(d, ulist);
-  launch_spmv(MODE_AP, false, V, d, alist, na, 0, s);
+  if (ncb > 0) {
+    // column blocks: each XCD gathers its own slice of the new column of P
+    launch_spmv(MODE_APB, false, VB, d, cblist, ncb, 0, s);
+    launch_apcomb(d, alist, na, s);
+  } else {
+    launch_spmv(MODE_AP, false, V, d, alist, na, 0, s);
+  }
   k_col_fin<<<ns, kPW, 0, s>>>(d, sys);
   PLSS_HIP(hipGetLastError());
 }

@@ -145,6 +145,23 @@ def test_mixed_underdetermined_medium(h):
     assert abs(full.iters - info["iters"]) <= 1
 
 
+def test_mixed_column_blocks(h):
+    """A wide underdetermined system (8,000 x 500,000: the new column of P,
+    4 MB, does not fit one XCD's L2), so the product A p runs over column
+    blocks of A (one per XCD) and their fixed-order sum; against the oracle
+    at equal update counts and converged."""
+    import paper_2207_07615_amd as plss
+    say("mixed column blocks")
+    sysm = gen.underdet(m=8000, n=500000)
+    M = matrix(h, sysm.A)
+    before = M.info()["device_bytes"]
+    plss.solve(h, M, sysm.b, sketch="mixed", tol=1e-300, maxit=2, row_perm=sysm.perm, hist_cap=32)
+    # the column-blocked copy of A was built by the first sketch solve
+    assert M.info()["device_bytes"] - before >= 12 * sysm.A.nnz
+    x, info, hist, ref = column_parity(h, sysm, "mixed", 1e-8, 2000, 32)
+    assert info["status"] == 0
+
+
 def dependent_rows_system(seed=61):
     """Identity-sketch system whose row order meets every branch of the skip
     rule (Section 7, eq. pkKacz; reading C7): 20 row pairs (u, u) with u =
