@@ -186,6 +186,17 @@ __device__ __forceinline__ T wave_seg_scan_excl(int f, T v) {
   return ex;
 }
 
+// wave maximum of an int (every lane gets it)
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// rows of at most this many entries: a tile whose rows are all this short is
+// summed one row per lane
+constexpr int kShortRow = 16;
+
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -327,6 +338,20 @@ __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
         }
       }
       wave_lds_sync();
+      // the tile's longest row (the same value in every lane)
+      int ml = 0;
+      for (int i = lane; i < nr; i += 64) ml = max(ml, so[i + 1] - so[i]);
+      ml = wave_max_i(ml);
+      if (ml <= kShortRow) {
+        // short rows: lane l sums rows l, l + 64, ... from their products, in
+        // order; no search for the lane's first row and no scan across lanes
+        for (int i = lane; i < nr; i += 64) {
+          const int e1 = so[i + 1];
+          Acc a = Acc(0);
+          for (int e = so[i]; e < e1; ++e) a += sp[e];
+          epi(r0 + i, a);
+        }
+      } else {
       // each lane sums V consecutive products, split at row ends
       const int c0 = lane * V;
       Acc acc = Acc(0);
@@ -374,6 +399,7 @@ __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
       }
       wave_lds_sync();
       for (int i = lane; i < nr; i += 64) epi(r0 + i, so[i] == so[i + 1] ? Acc(0) : sp[i]);
+      }
     }
   }
 
