@@ -132,6 +132,7 @@ struct Desc {
   const void* a_val;
   const int* a_tile;           // row start of every wave tile (a_nwt + 1)
   const int* a_grp;            // 4 wave tiles per group (-1 = none), a_ntiles groups
+  const int4* a_wtd;           // per (group, wave): {first row, end row, first entry, end entry}
   int a_nwt;                   // wave tiles
   int a_ntiles;                // groups of 4 wave tiles (one workgroup, one partial each)
   // CSC of A (= CSR of Aᵀ)
@@ -140,6 +141,7 @@ struct Desc {
   const void* t_val;
   const int* t_tile;
   const int* t_grp;
+  const int4* t_wtd;
   int t_nwt;
   int t_ntiles;
   int m, n;
@@ -155,6 +157,7 @@ struct Desc {
   const void* tb_val[kMaxBlk];
   const int* tb_tile[kMaxBlk];
   const int* tb_grp[kMaxBlk];
+  const int4* tb_wtd[kMaxBlk];
   void* ypart;                 // nblk x n block products (Vec)
   // column-blocked CSR: block b holds the entries of columns [cb[b], cb[b+1])
   int cnblk;                   // 1: products with A use the CSR above
@@ -163,6 +166,7 @@ struct Desc {
   const void* cb_val[kMaxBlk];
   const int* cb_tile[kMaxBlk];
   const int* cb_grp[kMaxBlk];
+  const int4* cb_wtd[kMaxBlk];
   double* appart;              // cnblk x m block products of A p (identity / mixed sketches)
   int phi_cnt;                 // partials of phi (t_ntiles, or u_nblk when blocked)
   // striped stores (used instead of the tiles when set)

@@ -152,15 +152,23 @@ __device__ __forceinline__ T seg_scan_excl(int f, T v, T* s_v, int* s_f) {
 // ------------------------------------------------------------------ phase guards
 
 // phase: the inner iteration runs while final_done == 0 and done == 0.
+// The state's fields are all read before any is tested (no short-circuit),
+// so their loads go out together.
 template <int MODE>
 __device__ __forceinline__ bool spmv_skip(const State* st) {
   if (MODE == MODE_PLAIN) return false;
-  if (MODE == MODE_REFINE) return st->final_done || !st->done;
-  if (MODE == MODE_TRANSB) return st->final_done || st->done;
-  if (st->final_done || st->done) return true;
-  if (MODE == MODE_RESID) return st->k == 0;
-  if (MODE == MODE_AP || MODE == MODE_APB) return st->skip != 0;
-  return false;
+  const int fd = st->final_done, dn = st->done;
+  if (MODE == MODE_REFINE) return (fd | (dn == 0)) != 0;
+  if (MODE == MODE_TRANSB || MODE == MODE_TRANS) return (fd | dn) != 0;
+  if (MODE == MODE_RESID) {
+    const long long k = st->k;
+    return ((fd | dn) != 0) | (k == 0);
+  }
+  if (MODE == MODE_AP || MODE == MODE_APB) {
+    const int sk = st->skip;
+    return (fd | dn | sk) != 0;
+  }
+  return (fd | dn) != 0;
 }
 
 // ------------------------------------------------------------------ tile SpMV
@@ -223,7 +231,6 @@ __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
   if (kBlk && ent.y < 0) return;  // padding of the XCD-interleaved list
   const Desc* d = D + ent.x;
   const State* st = d->st;
-  if (spmv_skip<MODE>(st)) return;
 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const bool tr = (MODE == MODE_TRANS) || (MODE == MODE_PLAIN && transpose);
@@ -235,10 +242,11 @@ __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
       MODE == MODE_TRANSB ? d->tb_idx[blk] : (MODE == MODE_APB ? d->cb_idx[blk] : (tr ? d->t_idx : d->a_idx));
   const Val* __restrict__ val = static_cast<const Val*>(
       MODE == MODE_TRANSB ? d->tb_val[blk] : (MODE == MODE_APB ? d->cb_val[blk] : (tr ? d->t_val : d->a_val)));
-  const int* __restrict__ tile =
-      MODE == MODE_TRANSB ? d->tb_tile[blk] : (MODE == MODE_APB ? d->cb_tile[blk] : (tr ? d->t_tile : d->a_tile));
-  const int* __restrict__ grp =
-      MODE == MODE_TRANSB ? d->tb_grp[blk] : (MODE == MODE_APB ? d->cb_grp[blk] : (tr ? d->t_grp : d->a_grp));
+  const int4* __restrict__ wtd =
+      MODE == MODE_TRANSB ? d->tb_wtd[blk] : (MODE == MODE_APB ? d->cb_wtd[blk] : (tr ? d->t_wtd : d->a_wtd));
+  // this wave's tile, read beside the state's flags (both before either is used)
+  const int4 wd = wtd[gi * kWaves + w];
+  if (spmv_skip<MODE>(st)) return;
 
   const Vin* __restrict__ xin;
   if (MODE == MODE_RESID) xin = static_cast<const Vin*>(d->p);
@@ -284,11 +292,10 @@ __global__ __launch_bounds__(kWG) void k_spmv(const Desc* __restrict__ D,
     }
   };
 
-  const int wt = grp[gi * kWaves + w];
-  if (wt >= 0) {
-    const int r0 = tile[wt], r1 = tile[wt + 1];
-    const int e0 = ptr[r0];
-    const int nr = r1 - r0, ne = ptr[r1] - e0;
+  if (wd.y > wd.x) {  // a wave past the group's last tile has none
+    const int r0 = wd.x, r1 = wd.y;
+    const int e0 = wd.z;
+    const int nr = r1 - r0, ne = wd.w - wd.z;
     if (ne > TW) {
       // one long row: the wave strides over it, 8 entries per lane in flight
       constexpr int U = 8;

@@ -145,6 +145,7 @@ void spmv_noalloc(plss_handle* h, const plss_matrix* A, bool transpose, const do
     d.a_ntiles = A->A.ntiles;
     d.a_nwt = A->A.nwt;
     d.a_grp = A->A.grp;
+    d.a_wtd = A->A.wtd;
     d.t_ptr = A->T.ptr;
     d.t_idx = A->T.idx;
     d.t_val = A->T.val;
@@ -152,6 +153,7 @@ void spmv_noalloc(plss_handle* h, const plss_matrix* A, bool transpose, const do
     d.t_ntiles = A->T.ntiles;
     d.t_nwt = A->T.nwt;
     d.t_grp = A->T.grp;
+    d.t_wtd = A->T.wtd;
   }
   // the descriptor goes from this stack frame: the copy is complete once the
   // stream is synchronised below, before the frame ends

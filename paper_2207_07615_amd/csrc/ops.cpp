@@ -33,6 +33,7 @@ void plain_launch(const plss_matrix* A, bool transpose, const double* dx, double
   d.a_ntiles = A->A.ntiles;
   d.a_nwt = A->A.nwt;
   d.a_grp = A->A.grp;
+  d.a_wtd = A->A.wtd;
   d.t_ptr = A->T.ptr;
   d.t_idx = A->T.idx;
   d.t_val = A->T.val;
@@ -40,6 +41,7 @@ void plain_launch(const plss_matrix* A, bool transpose, const double* dx, double
   d.t_ntiles = A->T.ntiles;
   d.t_nwt = A->T.nwt;
   d.t_grp = A->T.grp;
+  d.t_wtd = A->T.wtd;
   d.m = (int)A->m;
   d.n = (int)A->n;
   d.p = const_cast<double*>(dx);

@@ -75,14 +75,25 @@ std::vector<int> make_groups(const std::vector<int>& ptr, const std::vector<int>
 void set_tiles(PlssDir& d, int V, hipStream_t s) {
   std::vector<int> t = make_tiles(d.h_ptr, V);
   std::vector<int> g = make_groups(d.h_ptr, t, V);
+  // each wave's tile in one record, so a product reads its bounds with one
+  // load instead of group -> tile -> row pointer
+  std::vector<int4> wd(g.size());
+  for (size_t q = 0; q < g.size(); ++q) {
+    const int wt = g[q];
+    wd[q] = wt >= 0 ? make_int4(t[wt], t[wt + 1], d.h_ptr[t[wt]], d.h_ptr[t[wt + 1]]) : make_int4(0, 0, 0, 0);
+  }
   dfree(d.tile);
   dfree(d.grp);
+  dfree(d.wtd);
   d.tile = nullptr;
   d.grp = nullptr;
+  d.wtd = nullptr;
   d.tile = static_cast<int*>(dmalloc(sizeof(int) * t.size()));
   d.grp = static_cast<int*>(dmalloc(sizeof(int) * g.size()));
+  d.wtd = static_cast<int4*>(dmalloc(sizeof(int4) * std::max<size_t>(wd.size(), 1)));
   PLSS_HIP(hipMemcpyAsync(d.tile, t.data(), sizeof(int) * t.size(), hipMemcpyHostToDevice, s));
   PLSS_HIP(hipMemcpyAsync(d.grp, g.data(), sizeof(int) * g.size(), hipMemcpyHostToDevice, s));
+  if (!wd.empty()) PLSS_HIP(hipMemcpyAsync(d.wtd, wd.data(), sizeof(int4) * wd.size(), hipMemcpyHostToDevice, s));
   PLSS_HIP(hipStreamSynchronize(s));
   d.nwt = (int)t.size() - 1;
   d.ntiles = (int)g.size() / kWaves;
@@ -443,6 +454,7 @@ void matrix_destroy(plss_matrix* M) {
     dfree(d->val);
     dfree(d->tile);
     dfree(d->grp);
+    dfree(d->wtd);
     dfree(d->lrows);
   }
   for (int b = 0; b < kMaxBlk; ++b) {
@@ -451,12 +463,14 @@ void matrix_destroy(plss_matrix* M) {
     dfree(d.val);
     dfree(d.tile);
     dfree(d.grp);
+    dfree(d.wtd);
     free_stripes(M->SB[b]);
     PlssDir& c = M->CB[b];
     dfree(c.idx);
     dfree(c.val);
     dfree(c.tile);
     dfree(c.grp);
+    dfree(c.wtd);
   }
   free_stripes(M->SA);
   dfree(M->tb_ptr_all);
@@ -576,6 +590,7 @@ void build_col_blocks(plss_matrix* M, hipStream_t s) {
       dfree(d.val);
       dfree(d.tile);
       dfree(d.grp);
+      dfree(d.wtd);
     }
     dfree(ptr_all);
     dfree(d_cb);

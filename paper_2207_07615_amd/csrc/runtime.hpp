@@ -17,6 +17,7 @@ struct PlssDir {
   void* val = nullptr;   // nnz, f64 or f32
   int* tile = nullptr;   // nwt + 1 row starts of the wave tiles
   int* grp = nullptr;    // 4 * ntiles wave-tile ids (-1 = none)
+  int4* wtd = nullptr;   // 4 * ntiles: each wave's tile as {first row, end row, first entry, end entry} (zeros: none)
   int nwt = 0;           // wave tiles
   int ntiles = 0;        // groups of 4 wave tiles (workgroups per launch)
   int V = 8;             // entries per lane of a wave tile (64*V entries)

@@ -96,6 +96,7 @@ void sketch_solve(plss_handle* h, const plss_matrix* A, const double* b, const p
         d.cb_val[b] = A->CB[b].val;
         d.cb_tile[b] = A->CB[b].tile;
         d.cb_grp[b] = A->CB[b].grp;
+        d.cb_wtd[b] = A->CB[b].wtd;
       }
       d.appart = reinterpret_cast<double*>(extra + oAb);
     }

@@ -107,6 +107,7 @@ void SysRun::setup(const plss_matrix* M, const double* b_in, const plss_opts* o,
   desc.a_ntiles = M->A.ntiles;
   desc.a_nwt = M->A.nwt;
   desc.a_grp = M->A.grp;
+  desc.a_wtd = M->A.wtd;
   desc.t_ptr = M->T.ptr;
   desc.t_idx = M->T.idx;
   desc.t_val = M->T.val;
@@ -114,6 +115,7 @@ void SysRun::setup(const plss_matrix* M, const double* b_in, const plss_opts* o,
   desc.t_ntiles = M->T.ntiles;
   desc.t_nwt = M->T.nwt;
   desc.t_grp = M->T.grp;
+  desc.t_wtd = M->T.wtd;
   desc.m = (int)m;
   desc.n = (int)n;
   desc.a_long = M->A.lrows;
@@ -128,6 +130,7 @@ void SysRun::setup(const plss_matrix* M, const double* b_in, const plss_opts* o,
     desc.tb_val[b] = M->TB[b].val;
     desc.tb_tile[b] = M->TB[b].tile;
     desc.tb_grp[b] = M->TB[b].grp;
+    desc.tb_wtd[b] = M->TB[b].wtd;
   }
   desc.a_striped = as ? 1 : 0;
   desc.t_striped = ts ? 1 : 0;
