@@ -61,6 +61,17 @@ def rmatvec(S: sp.csr_matrix, v: np.ndarray) -> np.ndarray:
     return S.T @ v
 
 
+def residual_pair(S: sp.csr_matrix, p: np.ndarray, r: np.ndarray):
+    """The two matrix products of one iteration of Algorithm 1 (Section 5),
+    in the algorithm's order: the residual update r <- r - A p, then
+    y = Aᵀ r with the updated residual, and the squared norms of both
+    (rho = ||r||², phi = yᵀ y, i.e. W = I).  Returns (r, y, rho, phi); the
+    input r is not modified."""
+    r_new = np.asarray(r, dtype=np.float64) - matvec(S, np.asarray(p, dtype=np.float64))
+    y = rmatvec(S, r_new)
+    return r_new, y, float(r_new @ r_new), float(y @ y)
+
+
 def csr_to_csc(m, n, row_ptr, col_idx, vals):
     """Transpose storage: CSC of A with rows ascending inside every column.
 
