@@ -571,6 +571,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 + refinement arm")
     ap.add_argument("--no-w", action="store_true", help="skip the PLSS W arm (column-norm weights)")
     ap.add_argument("--no-rp", action="store_true", help="skip the randomized-projection arm")
+    ap.add_argument("--no-pair", action="store_true", help="skip the fused residual-pair measurement")
     ap.add_argument("--autotune", action="store_true", help="pick tile widths by measurement")
     ap.add_argument("--layout", default="auto", choices=["auto", "tiles", "stripes"],
                     help="product layout of the large workload (auto: chosen from the shape)")
@@ -766,6 +767,29 @@ def main():
         out["randproj_r5"] = {
             "iters": ir["iters"], "iters_per_s": ir["iters"] / wr, "ms_per_iter": 1e3 * wr / ir["iters"],
             "relres_true_after": ir["relres_true"], "plss_relres_true_after_same_iters": ip["relres_true"],
+        }
+
+    if not args.no_pair:
+        # the fused residual pair (one pass over the CSR, two-level sum for y)
+        # against the iteration's own products (both products, the block sum
+        # and the step scalars, from the timed solves above)
+        rng = np.random.default_rng(17)
+        pd = torch.from_numpy(rng.standard_normal(A.n)).to(dev)
+        rd = torch.from_numpy(rng.standard_normal(A.m)).to(dev)
+        plss.residual_pair(h, M, pd, rd)  # builds the position map
+        torch.cuda.synchronize()
+        npair = 10
+        t1 = time.perf_counter()
+        for _ in range(npair):
+            plss.residual_pair(h, M, pd, rd)
+        torch.cuda.synchronize()
+        wp = (time.perf_counter() - t1) / npair
+        pair_bytes = 32 * A.nnz + 20 * A.m + 20 * A.n
+        ref_ms = avg[0] + avg[1] + avg[2]
+        out["residual_pair"] = {
+            "ms_per_call": 1e3 * wp, "how": "host wall per call on device tensors (includes the call's sync)",
+            "bytes_per_call": pair_bytes, "gbps": pair_bytes / wp / 1e9,
+            "iteration_products_ms": ref_ms, "ratio_vs_iteration_products": 1e3 * wp / ref_ms,
         }
 
     if not args.no_cpu:

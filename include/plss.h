@@ -232,6 +232,27 @@ plss_status plss_spmv(plss_handle* h, const plss_matrix* A, int transpose, const
 plss_status plss_spmv_noalloc(plss_handle* h, const plss_matrix* A, int transpose, const double* x,
                               double* y);
 
+/* Both matrix products of one residual-sketch iteration (Algorithm 1,
+ * Section 5: the residual update with A p, then y = Aᵀ r with the updated
+ * residual) in one pass over the CSR store of A, as an alternative to the
+ * second pass over the transposed store:
+ *   r (length m, in/out): r <- r - A p;
+ *   y (length n, out):    y = Aᵀ r, with the updated r;
+ *   rho_phi (host, 2 doubles, may be NULL): ||r||² and ||y||² after the call.
+ * Level 1 streams the rows once: row i's dot product, the update of r_i, and
+ * the row's contributions a_ij r_i.  Level 2 sums column j's contributions
+ * in ascending row order.  Every sum has a fixed order, so results are
+ * bit-reproducible; float64 arithmetic over the stored (float64 or float32)
+ * values.  The first call on a matrix builds its map from transposed
+ * positions to row positions and a contribution buffer (4 + 8 bytes per
+ * entry), kept with the matrix until plss_matrix_destroy.  p, r and y may be
+ * host or device memory (device memory of the handle's GPU is used in
+ * place, otherwise the vectors are staged through the handle's workspace) and
+ * must not overlap.  Returns when r, y and rho_phi are complete.  Errors:
+ * EINVAL for null arguments, ENOMEM. */
+plss_status plss_residual_pair(plss_handle* h, plss_matrix* A, const double* p, double* r, double* y,
+                               double* rho_phi);
+
 /* Solve A x = b (b length m, x length n).  res_hist (may be NULL) receives
  * up to hist_cap entries sqrt(rho_k)/||b||, k = 0..iters (the recursive
  * residual of Algorithm 1).  Returns the system's status (OK, NOT_CONVERGED,

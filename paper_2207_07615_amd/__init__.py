@@ -274,6 +274,25 @@ def spmv(handle: Handle, A: Matrix, x, transpose=False):
     return y
 
 
+def residual_pair(handle: Handle, A: Matrix, p, r):
+    """r <- r - A p, then y = Aᵀ r with the updated r, in one pass over A
+    (plss_residual_pair).  p and r: host arrays or device tensors (the
+    caller's r is not modified).  Returns (r_new, y, rho, phi) with
+    rho = ||r_new||² and phi = ||y||²; vectors are of r's kind."""
+    pp = _Arr(p, np.float64)
+    rr = _Arr(r, np.float64)
+    if rr.torch:
+        r_new = rr.keep.clone()
+        rp = r_new.data_ptr()
+    else:
+        r_new = np.array(rr.keep, dtype=np.float64, copy=True)
+        rp = r_new.ctypes.data
+    y, yp = _out_like(rr, (A.n,))
+    out = (C.c_double * 2)()
+    _check(_clib().plss_residual_pair(handle.h, A.A, pp.ptr, rp, yp, out))
+    return r_new, y, out[0], out[1]
+
+
 def spmv_noalloc(handle: Handle, A: Matrix, x, y, transpose=False):
     """y <- A x (or Aᵀ x) through plss_spmv_noalloc: x and y are float64
     device tensors of the handle's GPU, y preallocated by the caller; the

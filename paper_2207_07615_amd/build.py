@@ -29,6 +29,7 @@ SOURCES = [
     "noalloc.hip",
     "block_kernels.hip",
     "randproj_kernels.hip",
+    "fused.hip",
     "runtime.cpp",
     "solve.cpp",
     "ops.cpp",
@@ -37,6 +38,7 @@ SOURCES = [
     "serve.cpp",
     "block.cpp",
     "randproj.cpp",
+    "pair.cpp",
     "abi.cpp",
 ]
 

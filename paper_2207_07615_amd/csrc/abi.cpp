@@ -4,6 +4,7 @@
 #include <string>
 #include <vector>
 
+#include "fused.hpp"
 #include "runtime.hpp"
 #include "sketch.hpp"
 #include "solve.hpp"
@@ -224,6 +225,17 @@ plss_status plss_spmv_noalloc(plss_handle* h, const plss_matrix* A, int transpos
   DeviceScope ds(h->device);
   std::lock_guard<std::mutex> lk(h->mu);
   spmv_noalloc(h, A, transpose != 0, x, y, h->stream);
+  return PLSS_OK;
+  PLSS_GUARD_END
+}
+
+plss_status plss_residual_pair(plss_handle* h, plss_matrix* A, const double* p, double* r, double* y,
+                               double* rho_phi) {
+  PLSS_GUARD_BEGIN
+  if (!h || !A || !p || !r || !y) throw InvalidArg{"null argument"};
+  DeviceScope ds(h->device);
+  std::lock_guard<std::mutex> lk(h->mu);
+  residual_pair(h, A, p, r, y, rho_phi, h->stream);
   return PLSS_OK;
   PLSS_GUARD_END
 }

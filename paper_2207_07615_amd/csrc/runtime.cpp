@@ -5,6 +5,8 @@
 #include <cmath>
 #include <cstring>
 
+#include "fused.hpp"
+
 namespace plss {
 
 void* dmalloc(size_t bytes) {
@@ -295,6 +297,7 @@ static void recount_bytes(plss_matrix* M) {
              sizeof(int) * (size_t)(M->A.ntiles + M->T.ntiles + 2) +
              (M->nblk > 1 ? sizeof(int) * (size_t)M->nblk * (n + 1) : 0);
   if (M->cnblk > 1) b += (size_t)nnz * (vsz + 4) + sizeof(int) * (size_t)M->cnblk * (m + 1);
+  if (M->fz_pos) b += (size_t)std::max<long long>(nnz, 1) * (sizeof(int) + sizeof(double));
   b += M->SA.bytes;
   for (int q = 0; q < kMaxBlk; ++q) b += M->SB[q].bytes;
   M->bytes = b;
@@ -475,6 +478,8 @@ void matrix_destroy(plss_matrix* M) {
   free_stripes(M->SA);
   dfree(M->tb_ptr_all);
   dfree(M->cb_ptr_all);
+  dfree(M->fz_pos);
+  dfree(M->fz_c);
   delete M;
 }
 
@@ -541,6 +546,25 @@ void build_row_blocks(plss_matrix* M, hipStream_t s, bool force) {
 // 4 MB L2; splitting the columns into 8 blocks of equal nnz gives every XCD
 // a slice that does.  Block b holds, row by row, the entries of its columns
 // (a contiguous sub-segment of each CSR row: column indices ascend).
+void build_fused(plss_matrix* M, hipStream_t s) {
+  if (M->fz_pos) return;
+  const size_t cnt = (size_t)std::max<long long>(M->nnz, 1);
+  int* pos = static_cast<int*>(dmalloc(sizeof(int) * cnt));
+  double* c = nullptr;
+  try {
+    c = static_cast<double*>(dmalloc(sizeof(double) * cnt));
+    if (M->nnz > 0) launch_fz_pos(M->A.ptr, M->A.idx, M->T.ptr, M->T.idx, (int)M->n, pos, s);
+    PLSS_HIP(hipStreamSynchronize(s));
+  } catch (...) {
+    dfree(pos);
+    dfree(c);
+    throw;
+  }
+  M->fz_pos = pos;
+  M->fz_c = c;
+  recount_bytes(M);
+}
+
 void build_col_blocks(plss_matrix* M, hipStream_t s) {
   const size_t vb = M->f32 ? 4 : 8;
   const long long m = M->m, n = M->n, nnz = M->nnz;

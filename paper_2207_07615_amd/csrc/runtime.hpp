@@ -75,6 +75,10 @@ struct plss_matrix {
   int cbnd[plss::kMaxBlk + 1] = {0};
   PlssDir CB[plss::kMaxBlk];
   int* cb_ptr_all = nullptr;   // cnblk x (m+1) pointers shared by the blocks
+  // fused residual pair: the CSR position of every CSC slot and the per-entry
+  // contributions a_ij r_i (float64); built on first use
+  int* fz_pos = nullptr;
+  double* fz_c = nullptr;
   // striped stores: SA for products with A, SB[b] for row block b of Aᵀ
   bool a_striped = false, t_striped = false;
   PlssStripes SA;
@@ -103,6 +107,9 @@ void build_row_blocks(plss_matrix* M, hipStream_t s, bool force = false);
 // Column blocks of A, when the gathered vector of a product with A (n
 // float64 entries) exceeds about 3 MB; a no-op once built or when it fits.
 void build_col_blocks(plss_matrix* M, hipStream_t s);
+// Position map and contribution buffer of the fused residual pair (12 bytes
+// per entry); a no-op once built.
+void build_fused(plss_matrix* M, hipStream_t s);
 size_t matrix_footprint(long long m, long long n, long long nnz, bool f32);
 
 // Striped layout: build or drop the stores (unit_rows 0 = from the shape).
