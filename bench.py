@@ -650,6 +650,8 @@ def main():
                       np.linalg.norm(sysm.xstar))
 
     bm = bytes_model(A.m, A.n, A.nnz)
+    lay_name = ("stripes" if layout["a_stripes"] and layout["t_stripes"]
+                else "tiles" if not (layout["a_stripes"] or layout["t_stripes"]) else "mixed")
     tot_iters = sum(iters)
     iters_per_s = tot_iters / wall
     avg = [kms[q] / max(1, kn[q]) for q in range(4)]
@@ -687,9 +689,11 @@ def main():
         "rel_err_vs_xstar": err_xstar,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": recorded_traffic(dom, "stripes" if layout["a_stripes"] and layout["t_stripes"]
-                                                 else "tiles" if not (layout["a_stripes"] or layout["t_stripes"])
-                                                 else "mixed"),
+                     "traffic": recorded_traffic(dom, lay_name),
+                     "traffic_source": ("recorded: calibrated rocprofv3 FETCH_SIZE / WRITE_SIZE passes of this "
+                                        "kernel (profiles/large_fp64_traffic.txt), reported only while the "
+                                        "kernel sources and the layout match those the counters were taken "
+                                        "with; not measured in this run"),
                      "kernel": (("k_sspmv RESID" if layout["a_stripes"] else "k_spmv RESID") +
                                 " (r -= A p, partial rho)") if dom == 0 else
                                (("k_sspmv TRANSB (row-block products A_b^T r_b)" if layout["t_stripes"]
