@@ -28,14 +28,14 @@ void residual_pair(plss_handle* h, plss_matrix* A, const double* p, double* r, d
   // device vectors are used in place; otherwise all three pass through the
   // handle's workspace
   const bool dev = on_device(p) && on_device(r) && on_device(y);
-  const int g1 = fz_grid(m), g2 = fz_grid(n);
+  const int g1 = fz_grid(m), gl = fz_long_grid(A->A.nlong), g2 = fz_grid(n);
   size_t off = 0;
   auto take = [&](size_t b) {
     const size_t o = off;
     off = up(off + b);
     return o;
   };
-  const size_t o_part = take(sizeof(double) * (size_t)(g1 + g2)), o_out = take(2 * sizeof(double));
+  const size_t o_part = take(sizeof(double) * (size_t)(g1 + gl + g2)), o_out = take(2 * sizeof(double));
   const size_t o_p = dev ? 0 : take(sizeof(double) * n), o_r = dev ? 0 : take(sizeof(double) * m);
   const size_t o_y = dev ? 0 : take(sizeof(double) * n);
   Workspace& ws = workspace(h);
@@ -50,8 +50,8 @@ void residual_pair(plss_handle* h, plss_matrix* A, const double* p, double* r, d
   }
   double* part = reinterpret_cast<double*>(ar + o_part);
   double* dout = reinterpret_cast<double*>(ar + o_out);
-  launch_fz_pair(A->f32, A->A.ptr, A->A.idx, A->A.val, (int)m, A->T.ptr, A->fz_pos, (int)n, dp, dr, A->fz_c, dy,
-                 part, dout, s);
+  launch_fz_pair(A->f32, A->A.ptr, A->A.idx, A->A.val, (int)m, A->A.lrows, A->A.nlong, A->T.ptr, A->fz_pos,
+                 (int)n, dp, dr, A->fz_c, dy, part, dout, s);
   PLSS_HIP(hipMemcpyAsync(hout, dout, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
   if (!dev) {
     PLSS_HIP(hipMemcpyAsync(r, dr, sizeof(double) * m, hipMemcpyDefault, s));

@@ -55,6 +55,10 @@ CASES = {
     "one_col": lambda: gen.make_csr(gen.rng_for(12), 5000, 1, np.ones(5000, dtype=np.int64), "normal"),
     # the large workload's Zipf row lengths, at a size the oracle runs in seconds
     "zipf": lambda: gen.large(m=60000, n=15000).A,
+    # 8000 rows of 1200 entries: every row is summed by a whole workgroup
+    # (four waves), and each row's contributions need the residual entry as
+    # it was before the row's update, in every wave
+    "long_rows": lambda: gen.make_csr(gen.rng_for(14), 8000, 20000, np.full(8000, 1200, dtype=np.int64), "normal"),
 }
 
 
