@@ -281,6 +281,8 @@ def residual_pair(handle: Handle, A: Matrix, p, r):
     rho = ||r_new||² and phi = ||y||²; vectors are of r's kind."""
     pp = _Arr(p, np.float64)
     rr = _Arr(r, np.float64)
+    if pp.keep.shape != (A.n,) or rr.keep.shape != (A.m,):
+        raise ValueError(f"p must hold {A.n} and r {A.m} entries (one-dimensional)")
     if rr.torch:
         r_new = rr.keep.clone()
         rp = r_new.data_ptr()

@@ -129,6 +129,27 @@ def test_residual_pair_device_tensors(h):
     assert rho == host[2] and phi == host[3]
 
 
+def test_residual_pair_errors(h):
+    """Null arguments return EINVAL through the C ABI; wrong lengths are
+    refused by the binding before any call."""
+    import paper_2207_07615_amd as plss
+    from paper_2207_07615_amd import _lib
+    say("residual pair: errors")
+    A = CASES["small"]()
+    M = matrix(h, A)
+    r = np.zeros(A.m)
+    y = np.zeros(A.n)
+    lib = _lib.load()
+    PLSS_EINVAL = -1
+    assert lib.plss_residual_pair(h.h, M.A, None, r.ctypes.data, y.ctypes.data, None) == PLSS_EINVAL
+    assert lib.plss_residual_pair(None, M.A, y.ctypes.data, r.ctypes.data, y.ctypes.data, None) == PLSS_EINVAL
+    assert lib.plss_residual_pair(h.h, None, y.ctypes.data, r.ctypes.data, y.ctypes.data, None) == PLSS_EINVAL
+    with pytest.raises(ValueError):
+        plss.residual_pair(h, M, np.zeros(A.n + 1), np.zeros(A.m))
+    with pytest.raises(ValueError):
+        plss.residual_pair(h, M, np.zeros(A.n), np.zeros(A.m - 1))
+
+
 def test_residual_pair_chained_iterations(h):
     """Three pairs in a row, each from the last one's r, against the oracle
     chained the same way (the position map and the contribution buffer are
