@@ -150,6 +150,19 @@ def test_residual_pair_errors(h):
         plss.residual_pair(h, M, np.zeros(A.n), np.zeros(A.m - 1))
 
 
+def test_residual_pair_no_entries(h):
+    """A matrix without stored entries: r is unchanged, y and ||y||² are zero."""
+    import paper_2207_07615_amd as plss
+    say("residual pair: no entries")
+    A = gen.make_csr(gen.rng_for(15), 6, 4, np.zeros(6, dtype=np.int64), "normal")
+    M = matrix(h, A)
+    r = np.arange(6.0) - 2.5
+    r1, y1, rho, phi = plss.residual_pair(h, M, np.ones(4), r)
+    np.testing.assert_array_equal(r1, r)
+    np.testing.assert_array_equal(y1, np.zeros(4))
+    assert rho == float(np.dot(r, r)) and phi == 0.0
+
+
 def test_residual_pair_chained_iterations(h):
     """Three pairs in a row, each from the last one's r, against the oracle
     chained the same way (the position map and the contribution buffer are
