@@ -139,11 +139,18 @@ void plss_opts_default(plss_opts* opts);
  * about 8 (m + n) hist_cap bytes; for the block sketches about
  * 8 (m + n) hist_cap bytes too (hist_cap up to 1024); for the randomized
  * projection 8 (m + n) r bytes (r rounded up to 4).  The largest such block a
- * handle has needed stays allocated until plss_destroy (a server created on
- * the handle does not count it in its HBM budget; use a separate handle for
- * sketch solves beside a server with a tight budget). */
+ * handle has needed stays allocated until plss_release_workspace or
+ * plss_destroy (a server created on the handle does not count it in its HBM
+ * budget; use a separate handle for sketch solves beside a server with a
+ * tight budget, or release the workspace after them). */
 plss_status plss_create(plss_handle** h, int device);
 plss_status plss_destroy(plss_handle* h);
+/* Free the handle's scratch described above (device blocks, pinned mirror,
+ * launch lists, events and second stream) after its pending work; the next
+ * call on the handle allocates afresh.  Matrices, servers and results are
+ * untouched, and results do not depend on it.  Errors: EINVAL for a null
+ * handle. */
+plss_status plss_release_workspace(plss_handle* h);
 
 /* Upload A and build its device store once: CSR with int32 pointers and the
  * CSC copy (rows ascending inside every column) used for the products with

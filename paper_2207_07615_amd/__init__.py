@@ -94,6 +94,10 @@ class Handle:
             _clib().plss_destroy(self.h)
             self.h = None
 
+    def release_workspace(self):
+        """Free the handle's grown scratch (plss_release_workspace)."""
+        _check(_clib().plss_release_workspace(self.h))
+
     def __del__(self):
         try:
             self.close()

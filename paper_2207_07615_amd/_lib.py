@@ -54,6 +54,7 @@ EXPORTS = {
     "plss_matrix_layout": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(plss_layout), C.POINTER(plss_layout)]),
     "plss_spmv": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "plss_spmv_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "plss_release_workspace": (C.c_int, [C.c_void_p]),
     "plss_residual_pair": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.POINTER(C.c_double)]),
     "plss_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(plss_opts), C.c_void_p,

@@ -229,6 +229,20 @@ plss_status plss_spmv_noalloc(plss_handle* h, const plss_matrix* A, int transpos
   PLSS_GUARD_END
 }
 
+plss_status plss_release_workspace(plss_handle* h) {
+  PLSS_GUARD_BEGIN
+  if (!h) throw InvalidArg{"null handle"};
+  DeviceScope ds(h->device);
+  std::lock_guard<std::mutex> lk(h->mu);
+  PLSS_HIP(hipStreamSynchronize(h->stream));
+  if (h->ws) {
+    workspace_free(h->ws);  // also waits for the second stream
+    h->ws = nullptr;
+  }
+  return PLSS_OK;
+  PLSS_GUARD_END
+}
+
 plss_status plss_residual_pair(plss_handle* h, plss_matrix* A, const double* p, double* r, double* y,
                                double* rho_phi) {
   PLSS_GUARD_BEGIN

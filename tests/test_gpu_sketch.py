@@ -131,6 +131,33 @@ def test_history_block_reuse_leaves_no_trace():
     np.testing.assert_array_equal(x2, x_ref)
 
 
+def test_release_workspace_keeps_results():
+    """plss_release_workspace frees a handle's scratch; the calls after it
+    (a mixed-sketch solve, a batch and a residual-sketch solve) allocate
+    afresh and give the same bits as before it; releasing twice is fine."""
+    import paper_2207_07615_amd as plss
+    say("release workspace")
+    hd = plss.Handle(0)
+    mid = gen.tiny(43, 900, 2500, 12, "uniform")
+    sq = gen.small(m=600, n=300)
+    Mm, Ms = matrix(hd, mid.A), matrix(hd, sq.A)
+    kw = dict(sketch="mixed", tol=1e-10, maxit=400, hist_cap=48, row_perm=mid.perm)
+
+    def run():
+        xm, im, _ = plss.solve(hd, Mm, mid.b, **kw)
+        xb, ib = plss.solve_batch(hd, [Ms, Ms], [sq.b, 2.0 * sq.b], tol=1e-10, maxit=2000)
+        xr, ir, _ = plss.solve(hd, Ms, sq.b, tol=1e-10, maxit=2000, engine="multi")
+        return [xm, xb[0], xb[1], xr], [im["iters"], ib[0]["iters"], ib[1]["iters"], ir["iters"]]
+
+    xs0, its0 = run()
+    hd.release_workspace()
+    hd.release_workspace()
+    xs1, its1 = run()
+    assert its0 == its1 and min(its0) > 0
+    for a, b in zip(xs0, xs1):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_mixed_underdetermined_medium(h):
     """The underdetermined recipe (30 nnz per row, U(-1,1)) at 20,000 x
     100,000, mixed sketch, tol 1e-8, against the oracle and A†b-consistency."""
