@@ -149,6 +149,12 @@ struct Desc {
   const int* a_long;
   const int* t_long;
   int a_nlong, t_nlong;
+  const int* a_sl_base;
+  const int* a_sl_idx;
+  const void* a_sl_val;
+  const int* t_sl_base;
+  const int* t_sl_idx;
+  const void* t_sl_val;
   int u_nblk;                  // blocks of the vector-update kernel
   // row-blocked CSC: block b holds the entries of rows [rb[b], rb[b+1])
   int nblk;                    // 1: products with Aᵀ use the CSC above

@@ -102,6 +102,58 @@ void set_tiles(PlssDir& d, int V, hipStream_t s) {
   d.V = V;
 }
 
+// Slice layout of a direction for the single-workgroup solve: rows of at most
+// 64 entries in slices of 64 rows, each slice as wide as its longest such row
+// (rounded up to 4); entry k of row 64 s + l at sl_base[s] + (k / 4) * 256 +
+// 4 l + k % 4, so the lanes of a wave, one row each, read 4 entries apiece from
+// one contiguous 1 KB (indices) span per load instead of from 64 rows apart.
+void set_slices(PlssDir& d, bool f32, hipStream_t s) {
+  const int nr = d.nrows, nsl = (nr + 63) / 64;
+  std::vector<int> base(nsl + 1, 0);
+  for (int q = 0; q < nsl; ++q) {
+    int w = 0;
+    for (int l = 0; l < 64; ++l) {
+      const int i = 64 * q + l;
+      if (i >= nr) break;
+      const int len = d.h_ptr[i + 1] - d.h_ptr[i];
+      if (len <= 64) w = std::max(w, len);
+    }
+    base[q + 1] = base[q] + (w + 3) / 4 * 4 * 64;
+  }
+  const long long nnz = d.h_ptr[nr];
+  const size_t vb = f32 ? 4 : 8, tot = std::max(base[nsl], 1);
+  std::vector<int> hidx((size_t)std::max<long long>(nnz, 1));
+  std::vector<char> hval((size_t)std::max<long long>(nnz, 1) * vb);
+  if (nnz > 0) {
+    PLSS_HIP(hipMemcpyAsync(hidx.data(), d.idx, sizeof(int) * nnz, hipMemcpyDeviceToHost, s));
+    PLSS_HIP(hipMemcpyAsync(hval.data(), d.val, vb * nnz, hipMemcpyDeviceToHost, s));
+    PLSS_HIP(hipStreamSynchronize(s));
+  }
+  std::vector<int> sidx(tot, 0);
+  std::vector<char> sval(tot * vb, 0);
+  for (int i = 0; i < nr; ++i) {
+    const int e0 = d.h_ptr[i], len = d.h_ptr[i + 1] - e0;
+    if (len > 64) continue;
+    const int sb = base[i / 64] + 4 * (i % 64);
+    for (int k = 0; k < len; ++k) {
+      const int o = sb + (k / 4) * 256 + k % 4;
+      sidx[o] = hidx[e0 + k];
+      std::memcpy(&sval[(size_t)o * vb], &hval[(size_t)(e0 + k) * vb], vb);
+    }
+  }
+  dfree(d.sl_base);
+  dfree(d.sl_idx);
+  dfree(d.sl_val);
+  d.sl_base = static_cast<int*>(dmalloc(sizeof(int) * (nsl + 1)));
+  d.sl_idx = static_cast<int*>(dmalloc(sizeof(int) * tot));
+  d.sl_val = dmalloc(vb * tot);
+  PLSS_HIP(hipMemcpyAsync(d.sl_base, base.data(), sizeof(int) * (nsl + 1), hipMemcpyHostToDevice, s));
+  PLSS_HIP(hipMemcpyAsync(d.sl_idx, sidx.data(), sizeof(int) * tot, hipMemcpyHostToDevice, s));
+  PLSS_HIP(hipMemcpyAsync(d.sl_val, sval.data(), vb * tot, hipMemcpyHostToDevice, s));
+  PLSS_HIP(hipStreamSynchronize(s));
+  d.sl_n = (long long)tot;
+}
+
 void set_long_rows(PlssDir& d, hipStream_t s) {
   std::vector<int> l;
   for (int i = 0; i < d.nrows; ++i)
@@ -121,7 +173,10 @@ size_t matrix_footprint(long long m, long long n, long long nnz, bool f32) {
   bool as = false, ts = false;
   auto_layout(m, n, nnz, f32, &as, &ts);
   const int copies = 2 + (blocked ? 1 : 0) + (as ? 1 : 0) + (ts ? 1 : 0);
-  return (size_t)nnz * (v + 4) * copies + (size_t)(m + n + 2) * 4 + (size_t)(m + n) / 64 * 4 +
+  // slice layouts of a system that fits the single-workgroup solve: at most
+  // 64 entries per row and direction, padding included
+  const size_t slices = small_fits((int)m, (int)n, f32) ? (size_t)64 * (m + n + 128) * (v + 4) : 0;
+  return slices + (size_t)nnz * (v + 4) * copies + (size_t)(m + n + 2) * 4 + (size_t)(m + n) / 64 * 4 +
          (blocked ? (size_t)kMaxBlk * (n + 1) * 4 : 0) + ((as || ts) ? (size_t)(m + n) / 64 * 4 + (1u << 20) : 0) +
          4096;
 }
@@ -298,6 +353,8 @@ static void recount_bytes(plss_matrix* M) {
              (M->nblk > 1 ? sizeof(int) * (size_t)M->nblk * (n + 1) : 0);
   if (M->cnblk > 1) b += (size_t)nnz * (vsz + 4) + sizeof(int) * (size_t)M->cnblk * (m + 1);
   if (M->fz_pos) b += (size_t)std::max<long long>(nnz, 1) * (sizeof(int) + sizeof(double));
+  for (const PlssDir* d : {&M->A, &M->T})
+    if (d->sl_base) b += (size_t)d->sl_n * (vsz + 4) + sizeof(int) * (size_t)((d->nrows + 63) / 64 + 1);
   b += M->SA.bytes;
   for (int q = 0; q < kMaxBlk; ++q) b += M->SB[q].bytes;
   M->bytes = b;
@@ -421,6 +478,10 @@ plss_matrix* matrix_create(plss_handle* h, const plss_csr* A, plss_dtype storage
     set_tiles(t, 8, s);
     set_long_rows(a, s);
     set_long_rows(t, s);
+    if (small_fits(m, n, M->f32)) {
+      set_slices(a, M->f32, s);
+      set_slices(t, M->f32, s);
+    }
     build_row_blocks(M, s);
   } catch (...) {
     if (d_v64 && d_v64 != M->A.val) dfree(d_v64);
@@ -459,6 +520,9 @@ void matrix_destroy(plss_matrix* M) {
     dfree(d->grp);
     dfree(d->wtd);
     dfree(d->lrows);
+    dfree(d->sl_base);
+    dfree(d->sl_idx);
+    dfree(d->sl_val);
   }
   for (int b = 0; b < kMaxBlk; ++b) {
     PlssDir& d = M->TB[b];

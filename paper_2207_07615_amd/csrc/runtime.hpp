@@ -22,6 +22,13 @@ struct PlssDir {
   int ntiles = 0;        // groups of 4 wave tiles (workgroups per launch)
   int V = 8;             // entries per lane of a wave tile (64*V entries)
   int* lrows = nullptr;  // rows of more than 64 entries (single-workgroup solve)
+  // slice layout for the single-workgroup solve: slice s (rows 64 s .. 64 s + 63)
+  // starts at sl_base[s]; entry k of its row 64 s + l is at
+  // sl_base[s] + (k / 4) * 256 + 4 l + k % 4 (rows of at most 64 entries)
+  int* sl_base = nullptr;
+  int* sl_idx = nullptr;
+  void* sl_val = nullptr;
+  long long sl_n = 0;     // entries of the slice layout, padding included
   int nlong = 0;
   std::vector<int> h_ptr;  // host copy of ptr (tile construction)
 };
@@ -98,6 +105,8 @@ std::vector<int> make_tiles(const std::vector<int>& ptr, int V);
 std::vector<int> make_groups(const std::vector<int>& ptr, const std::vector<int>& tiles, int V);
 void set_tiles(PlssDir& d, int V, hipStream_t s);
 void set_long_rows(PlssDir& d, hipStream_t s);
+// slice layout of a direction for the single-workgroup solve (runtime.cpp)
+void set_slices(PlssDir& d, bool f32, hipStream_t s);
 
 // validated store creation (throws InvalidArg / OutOfMemory / DeviceError)
 plss_matrix* matrix_create(plss_handle* h, const plss_csr* A, plss_dtype storage, hipStream_t s);

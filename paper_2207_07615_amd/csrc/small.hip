@@ -7,7 +7,10 @@
 // Here one workgroup runs the whole solve: x, r, p, y and both row-pointer
 // arrays live in LDS, the matrix entries (CSR and CSC) are read from L2,
 // every reduction is a fixed-order
-// workgroup sum, and the phases are separated by workgroup barriers.  The
+// workgroup sum, and the phases are separated by workgroup barriers.  Rows
+// of at most 64 entries are read from the matrix's slice layout (a wave's 64
+// rows side by side, four entries per lane and load); the sum of each row
+// keeps its entry order.  The
 // decisions are those of the multi-kernel path (k_outer, k_start, k_step,
 // k_update): the same stop test, breakdown and iteration-limit rules, the
 // same refinement restarts and the same per-row arithmetic, so a system
@@ -84,21 +87,29 @@ __device__ __forceinline__ void sm_sum2(double& a, double& b, double* s_red, int
 template <class Val, class Acc, class Vin, class Epi>
 __device__ __forceinline__ void sm_rows(const int* __restrict__ ptr, const int* __restrict__ idx,
                                         const Val* __restrict__ val, int nrows, const int* __restrict__ lrows,
-                                        int nlong, const Vin* __restrict__ v, Epi epi) {
+                                        int nlong, const Vin* __restrict__ v, const int* __restrict__ sl_base,
+                                        const int* __restrict__ sl_idx, const Val* __restrict__ sl_val, Epi epi) {
   for (int i = threadIdx.x; i < nrows; i += kSmT) {
-    const int e0 = ptr[i], e1 = ptr[i + 1];
-    if (e1 - e0 > kLongRow) continue;
+    const int len = ptr[i + 1] - ptr[i];
+    if (len > kLongRow) continue;
     Acc s = Acc(0);
-    int e = e0;
-    for (; e + 4 <= e1; e += 4) {
-      const int c0 = gload(&idx[e]), c1 = gload(&idx[e + 1]), c2 = gload(&idx[e + 2]), c3 = gload(&idx[e + 3]);
-      const Val v0 = gload(&val[e]), v1 = gload(&val[e + 1]), v2 = gload(&val[e + 2]), v3 = gload(&val[e + 3]);
+    const int sb = gload(&sl_base[i >> 6]) + 4 * (i & 63);
+    int k = 0;
+    for (; k + 4 <= len; k += 4) {
+      const int o = sb + (k >> 2) * 256;
+      const int c0 = gload(&sl_idx[o]), c1 = gload(&sl_idx[o + 1]), c2 = gload(&sl_idx[o + 2]),
+                c3 = gload(&sl_idx[o + 3]);
+      const Val v0 = gload(&sl_val[o]), v1 = gload(&sl_val[o + 1]), v2 = gload(&sl_val[o + 2]),
+                v3 = gload(&sl_val[o + 3]);
       s += Acc(v0) * Acc(v[c0]);
       s += Acc(v1) * Acc(v[c1]);
       s += Acc(v2) * Acc(v[c2]);
       s += Acc(v3) * Acc(v[c3]);
     }
-    for (; e < e1; ++e) s += Acc(gload(&val[e])) * Acc(v[gload(&idx[e])]);
+    for (; k < len; ++k) {
+      const int o = sb + (k >> 2) * 256 + (k & 3);
+      s += Acc(gload(&sl_val[o])) * Acc(v[gload(&sl_idx[o])]);
+    }
     epi(i, s);
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -145,6 +156,12 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
   const int a_nlong = d->a_nlong, t_nlong = d->t_nlong;
   const Val* __restrict__ aval = static_cast<const Val*>(d->a_val);
   const Val* __restrict__ tval = static_cast<const Val*>(d->t_val);
+  const int* __restrict__ a_slb = d->a_sl_base;
+  const int* __restrict__ a_sli = d->a_sl_idx;
+  const Val* __restrict__ a_slv = static_cast<const Val*>(d->a_sl_val);
+  const int* __restrict__ t_slb = d->t_sl_base;
+  const int* __restrict__ t_sli = d->t_sl_idx;
+  const Val* __restrict__ t_slv = static_cast<const Val*>(d->t_sl_val);
   const double* __restrict__ bvec = d->b;
   double* __restrict__ r64 = d->r64;
   const double* __restrict__ wi = d->wi;
@@ -175,7 +192,7 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
       __syncthreads();
     }
     double rr = 0.0, bb = 0.0;
-    sm_rows<Val, double, double>(a_ptr_l, a_idx, aval, m, a_long, a_nlong, xo, [&](int i, double s) {
+    sm_rows<Val, double, double>(a_ptr_l, a_idx, aval, m, a_long, a_nlong, xo, a_slb, a_sli, a_slv, [&](int i, double s) {
       const double bi = gload(&bvec[i]);
       const double ri = bi - s;
       gstore(&r64[i], ri);
@@ -234,7 +251,7 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
     for (long long k = 0;; ++k) {
       if (k > 0) {
         double rp = 0.0, unused2 = 0.0;
-        sm_rows<Val, Vec, Vec>(a_ptr_l, a_idx, aval, m, a_long, a_nlong, p, [&](int i, Vec s) {
+        sm_rows<Val, Vec, Vec>(a_ptr_l, a_idx, aval, m, a_long, a_nlong, p, a_slb, a_sli, a_slv, [&](int i, Vec s) {
           const Vec rn = Vec(r[i] - s);
           r[i] = rn;
           rp += double(rn) * double(rn);
@@ -252,7 +269,7 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
         break;
       }
       double ph = 0.0, unused3 = 0.0;
-      sm_rows<Val, Vec, Vec>(t_ptr_l, t_idx, tval, n, t_long, t_nlong, r, [&](int i, Vec s) {
+      sm_rows<Val, Vec, Vec>(t_ptr_l, t_idx, tval, n, t_long, t_nlong, r, t_slb, t_sli, t_slv, [&](int i, Vec s) {
         y[i] = s;
         const double ds = double(s);
         ph += wi ? ds * ds / gload(&wi[i]) : ds * ds;

@@ -122,6 +122,12 @@ void SysRun::setup(const plss_matrix* M, const double* b_in, const plss_opts* o,
   desc.t_long = M->T.lrows;
   desc.a_nlong = M->A.nlong;
   desc.t_nlong = M->T.nlong;
+  desc.a_sl_base = M->A.sl_base;
+  desc.a_sl_idx = M->A.sl_idx;
+  desc.a_sl_val = M->A.sl_val;
+  desc.t_sl_base = M->T.sl_base;
+  desc.t_sl_idx = M->T.sl_idx;
+  desc.t_sl_val = M->T.sl_val;
   desc.u_nblk = u_nblk;
   desc.nblk = M->nblk;
   for (int b = 0; b < M->nblk && M->nblk > 1; ++b) {

@@ -54,6 +54,24 @@ def long_cols_system(seed=33):
     return gen.consistent(gen.rng_for(seed + 1), A)
 
 
+def row_mix_system(seed=35, m=1063, n=1500):
+    """Row lengths 0..64 mixed inside each slice of 64 rows (rows of exactly
+    64 entries, the longest read from the slice layout; rows of 65 and 70,
+    the shortest summed by whole waves), a last slice of 39 rows, rows scaled
+    to unit norm; columns of every length up to about 60."""
+    rng = gen.rng_for(seed)
+    L = rng.integers(0, 65, size=m)
+    L[::7] = 64
+    L[5::11] = 65
+    L[9::13] = 70
+    L[2::17] = 0
+    A = gen.make_csr(rng, m, n, L, "normal")
+    nrm = np.sqrt(np.add.reduceat(A.vals ** 2, A.row_ptr[:-1]))
+    nrm[np.diff(A.row_ptr) == 0] = 1.0
+    A.vals = A.vals / np.repeat(nrm, np.diff(A.row_ptr))
+    return gen.consistent(rng, A)
+
+
 def test_small_engine_small_workload(h):
     """2000 x 1000, 8 entries per row, FP64, tol 1e-8: the oracle protocol."""
     say("single engine: small workload")
@@ -62,7 +80,7 @@ def test_small_engine_small_workload(h):
     assert info["relres_true"] <= 1.5e-8
 
 
-@pytest.mark.parametrize("case", ["small", "wide", "long_rows", "long_cols", "W"])
+@pytest.mark.parametrize("case", ["small", "wide", "long_rows", "long_cols", "row_mix", "W"])
 def test_engines_agree(h, case):
     import paper_2207_07615_amd as plss
     say("engines agree", case)
@@ -75,6 +93,8 @@ def test_engines_agree(h, case):
         sysm = long_rows_system()
     elif case == "long_cols":
         sysm = long_cols_system()
+    elif case == "row_mix":
+        sysm = row_mix_system()
     else:
         sysm = gen.small(m=3000, n=1500)
         wi = np.sqrt(np.asarray(sysm.A.scipy().multiply(sysm.A.scipy()).sum(axis=0)).ravel())
