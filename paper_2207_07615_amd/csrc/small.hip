@@ -93,7 +93,7 @@ __device__ __forceinline__ void sm_rows(const int* __restrict__ ptr, const int* 
     const int len = ptr[i + 1] - ptr[i];
     if (len > kLongRow) continue;
     Acc s = Acc(0);
-    const int sb = gload(&sl_base[i >> 6]) + 4 * (i & 63);
+    const int sb = sl_base[i >> 6] + 4 * (i & 63);
     int k = 0;
     for (; k + 4 <= len; k += 4) {
       const int o = sb + (k >> 2) * 256;
@@ -136,8 +136,8 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
   State* st = d->st;
   const int m = d->m, n = d->n;
   const bool f32 = d->is_f32 != 0;
-  // LDS: x (float64), r, p, y (Vec), then the row pointers of both
-  // directions (the layout small_fits() checks)
+  // LDS: x (float64), r, p, y (Vec), then the row pointers and the slice
+  // starts of both directions (the layout small_fits() checks)
   const int ma = (m + 31) & ~31, na = (n + 31) & ~31;
   double* xl = s_mem;
   Vec* r = reinterpret_cast<Vec*>(xl + na);
@@ -145,6 +145,9 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
   Vec* y = p + na;
   int* a_ptr_l = reinterpret_cast<int*>(y + na);
   int* t_ptr_l = a_ptr_l + ((m + 1 + 31) & ~31);
+  const int nsa = (m + 63) / 64, nst = (n + 63) / 64;
+  int* a_slb_l = t_ptr_l + ((n + 1 + 31) & ~31);
+  int* t_slb_l = a_slb_l + ((nsa + 31) & ~31);
   // the descriptor's fields as restricted locals (stores to the vectors below
   // cannot then force the compiler to reread the descriptor)
   const int* __restrict__ a_ptr = d->a_ptr;
@@ -172,6 +175,8 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
   const long long hist_len = d->hist_len;
   for (int i = threadIdx.x; i <= m; i += kSmT) a_ptr_l[i] = gload(&a_ptr[i]);
   for (int i = threadIdx.x; i <= n; i += kSmT) t_ptr_l[i] = gload(&t_ptr[i]);
+  for (int i = threadIdx.x; i < nsa; i += kSmT) a_slb_l[i] = gload(&a_slb[i]);
+  for (int i = threadIdx.x; i < nst; i += kSmT) t_slb_l[i] = gload(&t_slb[i]);
   __syncthreads();
 
   const double tol = st->tol, tol_out = st->tol_out, inner_tol = st->inner_tol;
@@ -192,7 +197,7 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
       __syncthreads();
     }
     double rr = 0.0, bb = 0.0;
-    sm_rows<Val, double, double>(a_ptr_l, a_idx, aval, m, a_long, a_nlong, xo, a_slb, a_sli, a_slv, [&](int i, double s) {
+    sm_rows<Val, double, double>(a_ptr_l, a_idx, aval, m, a_long, a_nlong, xo, a_slb_l, a_sli, a_slv, [&](int i, double s) {
       const double bi = gload(&bvec[i]);
       const double ri = bi - s;
       gstore(&r64[i], ri);
@@ -251,7 +256,7 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
     for (long long k = 0;; ++k) {
       if (k > 0) {
         double rp = 0.0, unused2 = 0.0;
-        sm_rows<Val, Vec, Vec>(a_ptr_l, a_idx, aval, m, a_long, a_nlong, p, a_slb, a_sli, a_slv, [&](int i, Vec s) {
+        sm_rows<Val, Vec, Vec>(a_ptr_l, a_idx, aval, m, a_long, a_nlong, p, a_slb_l, a_sli, a_slv, [&](int i, Vec s) {
           const Vec rn = Vec(r[i] - s);
           r[i] = rn;
           rp += double(rn) * double(rn);
@@ -269,7 +274,7 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
         break;
       }
       double ph = 0.0, unused3 = 0.0;
-      sm_rows<Val, Vec, Vec>(t_ptr_l, t_idx, tval, n, t_long, t_nlong, r, t_slb, t_sli, t_slv, [&](int i, Vec s) {
+      sm_rows<Val, Vec, Vec>(t_ptr_l, t_idx, tval, n, t_long, t_nlong, r, t_slb_l, t_sli, t_slv, [&](int i, Vec s) {
         y[i] = s;
         const double ds = double(s);
         ph += wi ? ds * ds / gload(&wi[i]) : ds * ds;
@@ -332,7 +337,9 @@ __global__ __launch_bounds__(kSmT) void k_small(const Desc* __restrict__ D, cons
 bool small_fits(int m, int n, bool f32) {
   const size_t vb = f32 ? 4 : 8;
   const size_t ma = (size_t)((m + 31) & ~31), na = (size_t)((n + 31) & ~31);
-  const size_t bytes = 8 * na + vb * (ma + 2 * na) + 4 * ((size_t)((m + 1 + 31) & ~31) + (size_t)(n + 1));
+  const size_t slices = (size_t)((((m + 63) / 64) + 31) & ~31) + (size_t)((n + 63) / 64);
+  const size_t bytes = 8 * na + vb * (ma + 2 * na) +
+                       4 * ((size_t)((m + 1 + 31) & ~31) + (size_t)((n + 1 + 31) & ~31) + slices);
   return bytes <= kSmallLds;
 }
 
