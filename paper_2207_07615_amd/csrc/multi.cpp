@@ -139,7 +139,7 @@ plss_status run_group(plss_handle* h, const plss_matrix* A, int ncols, const dou
         if (e) PLSS_HIP(hipEventRecord(e[1], s));
         launch_spmm(MMODE_TRANS, f32, W, dd, nt_blk, s);
         if (e) PLSS_HIP(hipEventRecord(e[2], s));
-        launch_mstep(dd, s);
+        launch_mstep(dd, W, s);
         if (e) PLSS_HIP(hipEventRecord(e[3], s));
         launch_mupdate(f32, dd, nu_blk, s);
         if (e) PLSS_HIP(hipEventRecord(e[4], s));

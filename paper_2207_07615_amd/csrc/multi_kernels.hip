@@ -151,22 +151,51 @@ __device__ void col_sums(const double* __restrict__ part, int nb, int s, double*
 }
 
 // Per-column scalars of Algorithm 1 (one workgroup).
-__global__ __launch_bounds__(kMW) void k_mstep(const MDesc* __restrict__ d) {
-  __shared__ double s_tmp[kMW];
-  __shared__ double s_rho[64], s_phi[64], s_theta[64], s_nb[64];
+// One workgroup per column: the column's block partials of rho, phi, theta
+// (and of ||b||², needed only at an inner start) summed in a fixed order -
+// thread t adds blocks t, t + kMS, ... in order, then a tree over the
+// threads - with every load of the column issued together; then the
+// column's step scalars.
+constexpr int kMS = 256;
+
+__device__ __forceinline__ double tree_sum(double v, double* s_buf) {
+  s_buf[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kMS / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s_buf[threadIdx.x] += s_buf[threadIdx.x + w];
+    __syncthreads();
+  }
+  return s_buf[0];
+}
+
+__global__ __launch_bounds__(kMS) void k_mstep(const MDesc* __restrict__ d) {
+  __shared__ double s_buf[4][kMS];
   MState* st = d->st;
   if (st->all_done) return;
-  const int s = d->s;
-  col_sums(d->part_rho, d->na_blk, s, s_tmp, s_rho);
-  col_sums(d->part_phi, d->nt_blk, s, s_tmp, s_phi);
-  col_sums(d->part_theta, d->nu_blk, s, s_tmp, s_theta);
-  col_sums(d->part_b, d->na_blk, s, s_tmp, s_nb);
-  const int c = threadIdx.x;
-  if (c >= s || st->done[c]) return;
+  const int s = d->s, c = blockIdx.x;
+  if (st->done[c]) return;  // the same for the whole workgroup
   const long long k = st->k[c];
-  const double rho = s_rho[c], phi = s_phi[c];
+  const bool want_b = k == 0;
+  const int nmax = max(d->na_blk, max(d->nt_blk, d->nu_blk));
+  double a_rho = 0.0, a_phi = 0.0, a_theta = 0.0, a_b = 0.0;
+  for (int b = threadIdx.x; b < nmax; b += kMS) {
+    const size_t o = (size_t)b * s + c;
+    const double vr = b < d->na_blk ? d->part_rho[o] : 0.0;
+    const double vp = b < d->nt_blk ? d->part_phi[o] : 0.0;
+    const double vt = b < d->nu_blk ? d->part_theta[o] : 0.0;
+    const double vb = want_b && b < d->na_blk ? d->part_b[o] : 0.0;
+    a_rho += vr;
+    a_phi += vp;
+    a_theta += vt;
+    a_b += vb;
+  }
+  const double rho = tree_sum(a_rho, s_buf[0]);
+  const double phi = tree_sum(a_phi, s_buf[1]);
+  const double theta_sum = tree_sum(a_theta, s_buf[2]);
+  const double nb2 = want_b ? tree_sum(a_b, s_buf[3]) : 0.0;
+  if (threadIdx.x != 0) return;
   if (k == 0) {
-    const double nb = sqrt(s_nb[c]);
+    const double nb = sqrt(nb2);
     st->nb[c] = nb;
     double eta = st->inner_tol;
     if (d->is_f32) {
@@ -201,7 +230,7 @@ __global__ __launch_bounds__(kMW) void k_mstep(const MDesc* __restrict__ d) {
     beta = 0.0;
     gamma = rho / phi;
   } else {
-    const double theta = s_theta[c];
+    const double theta = theta_sum;
     const double sr = sqrt(theta * phi) / rho;
     if (!(sr > 1.0)) {
       st->status[c] = ST_BREAKDOWN;
@@ -409,7 +438,7 @@ void launch_spmm(int mode, bool f32, int W, const MDesc* d, int grid, hipStream_
   PLSS_HIP(hipGetLastError());
 }
 
-void launch_mstep(const MDesc* d, hipStream_t s) { k_mstep<<<1, kMW, 0, s>>>(d); }
+void launch_mstep(const MDesc* d, int ncols, hipStream_t s) { k_mstep<<<ncols, kMS, 0, s>>>(d); }
 void launch_mouter(const MDesc* d, hipStream_t s) { k_mouter<<<1, kMW, 0, s>>>(d); }
 void launch_mupdate(bool f32, const MDesc* d, int grid, hipStream_t s) {
   if (f32) k_mupdate<float><<<grid, kMB, 0, s>>>(d);

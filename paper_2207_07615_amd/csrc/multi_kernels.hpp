@@ -52,7 +52,7 @@ struct MDesc {
 };
 
 void launch_spmm(int mode, bool f32, int W, const MDesc* d, int grid, hipStream_t s);
-void launch_mstep(const MDesc* d, hipStream_t s);
+void launch_mstep(const MDesc* d, int ncols, hipStream_t s);  // ncols = MDesc::s
 void launch_mouter(const MDesc* d, hipStream_t s);
 void launch_mupdate(bool f32, const MDesc* d, int grid, hipStream_t s);
 void launch_mstart(bool f32, const MDesc* d, int grid, hipStream_t s);
