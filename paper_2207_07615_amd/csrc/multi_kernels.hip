@@ -256,25 +256,42 @@ __global__ __launch_bounds__(kMB) void k_mupdate(const MDesc* __restrict__ d) {
   if (st->all_done) return;
   const int s = d->s;
   const long long total = (long long)d->n * s;
-  Vec* P = static_cast<Vec*>(d->P);
-  const Vec* Y = static_cast<const Vec*>(d->Y);
-  double* X = d->Xi;
+  Vec* __restrict__ P = static_cast<Vec*>(d->P);
+  const Vec* __restrict__ Y = static_cast<const Vec*>(d->Y);
+  double* __restrict__ X = d->Xi;
   // kMB threads x 16 elements; s divides kMB (s a power of two here) so each
-  // thread stays on one column
+  // thread stays on one column.  In each of two passes, eight elements'
+  // loads go out before any store (the three arrays are distinct), then the
+  // elements are updated in order.
   const long long base = (long long)blockIdx.x * kUE;
   const int c = threadIdx.x % s;
   double part = 0.0;
   if (!st->done[c]) {
     const double beta = st->beta[c], gamma = st->gamma[c];
     const bool fresh = st->fresh[c] != 0;
-    for (int u = 0; u < 16; ++u) {
-      const long long o = base + (long long)u * kMB + threadIdx.x;
-      if (o < total) {
-        const double pn = fresh ? gamma * double(Y[o]) : beta * double(P[o]) + gamma * double(Y[o]);
-        const Vec pv = Vec(pn);
-        P[o] = pv;
-        X[o] += double(pv);
-        part += double(pv) * double(pv);
+    constexpr int U = 8;  // two passes of eight elements
+    for (int h = 0; h < 2; ++h) {
+      const long long hb = base + (long long)h * U * kMB + threadIdx.x;
+      Vec pv[U], yv[U];
+      double xv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const long long o = hb + (long long)u * kMB;
+        const bool in = o < total;
+        pv[u] = in ? P[o] : Vec(0);
+        yv[u] = in ? Y[o] : Vec(0);
+        xv[u] = in ? X[o] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const long long o = hb + (long long)u * kMB;
+        if (o < total) {
+          const double pn = fresh ? gamma * double(yv[u]) : beta * double(pv[u]) + gamma * double(yv[u]);
+          const Vec pq = Vec(pn);
+          P[o] = pq;
+          X[o] = xv[u] + double(pq);
+          part += double(pq) * double(pq);
+        }
       }
     }
   }
